@@ -1,0 +1,381 @@
+"""FP64 CPU oracle: 3D-FSR Tikhonov closed form and TV-ADMM (Algorithm 1).
+
+TEST INFRASTRUCTURE ONLY -- imported by tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py, never by the HIP library or its binding.
+
+Everything is float64 / complex128, written for a reader holding the paper
+(Tuador et al., "A Novel Fast 3D Single Image Super-Resolution Algorithm",
+arXiv 2010.15491). Each function names the passage it follows. There is no
+blocking, fusion or reordering beyond what the cited formula states; library
+primitives used as steps are scipy.fft (unnormalised 3D DFT) and
+numpy.linalg.solve.
+
+Conventions (readings of the paper, each listed in the design doc):
+  * A volume of size m x n x s (m = rows, fastest in the lexicographic order of
+    Sec. II-A and the Kronecker order of eq. (8)) is a C-order array of shape
+    (s, n, m).
+  * ``rate = (dr, dc, ds)``: dr decimates m, dc decimates n, ds decimates s.
+    D keeps the voxel at offset 0 of every dr x dc x ds block.
+  * Lambda is the unnormalised 3D DFT of the PSF zero-padded to the HR grid and
+    circularly shifted so the PSF's centre voxel (index K//2 per axis) sits at
+    index 0 -- i.e. of the first column of the circulant H (eq. (2)).
+  * r = d = dr * dc * ds (eq. (9), (12), Algorithm 1 input).
+  * L stacks periodic forward differences along m, n, s (component order
+    h = m, v = n, s = s); isotropic TV sum_j ||(Lx)_j||_2 (the shrink of
+    Algorithm 1 step 5b).
+  * Gamma = 1/G is unbounded at the zero frequency (Algorithm 1 step 4); the one
+    alias group holding k = 0 is solved as its own d x d linear system.
+  * Stopping rule: relative primal/dual residuals (the rule of the ADMM
+    reference the paper cites), tested after every iteration.
+"""
+
+from __future__ import annotations
+
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.fft as sfft
+
+__all__ = [
+    "WORKERS", "hr_shape_of", "lr_shape_of", "psf_to_otf", "blur", "blur_adjoint",
+    "decimate", "zero_fill", "degrade", "fold", "unfold", "diff_symbol_sq",
+    "grad", "grad_adjoint", "shrink", "tikhonov", "tikhonov_objective",
+    "x_update", "AdmmResult", "admm_tv", "tv_objective", "data_term", "psnr",
+    "rel_l2",
+]
+
+WORKERS = os.cpu_count() or 1
+
+
+def _fftn(a):
+    return sfft.fftn(a, workers=WORKERS)
+
+
+def _ifftn(a):
+    return sfft.ifftn(a, workers=WORKERS)
+
+
+# ---------------------------------------------------------------------------
+# Degradation model, Sec. II-A, eq. (1)-(2)
+# ---------------------------------------------------------------------------
+
+def _axes_rate(rate):
+    """(dr, dc, ds) -> per-array-axis factors (ds, dc, dr) for shape (s, n, m)."""
+    dr, dc, ds = rate
+    return (ds, dc, dr)
+
+
+def hr_shape_of(lr_shape, rate):
+    """m_h = m_l*dr, n_h = n_l*dc, s_h = s_l*ds (Sec. II-A)."""
+    f = _axes_rate(rate)
+    return tuple(int(a) * int(b) for a, b in zip(lr_shape, f))
+
+
+def lr_shape_of(hr_shape, rate):
+    f = _axes_rate(rate)
+    for a, b in zip(hr_shape, f):
+        if a % b:
+            raise ValueError("HR size not divisible by its decimation rate")
+    return tuple(int(a) // int(b) for a, b in zip(hr_shape, f))
+
+
+def psf_to_otf(psf, hr_shape):
+    """Lambda of eq. (2): 3D DFT of the zero-padded PSF (first column of H).
+
+    The PSF (shape (Ks, Kn, Km)) is placed in an all-zero HR volume and rolled
+    by -(K//2) per axis, so that H is a circular convolution centred on the
+    PSF's middle voxel. Unnormalised DFT, as the diagonal of H = F^H Lambda F
+    with F unitary.
+    """
+    psf = np.asarray(psf, dtype=np.float64)
+    if any(k > n for k, n in zip(psf.shape, hr_shape)):
+        raise ValueError("PSF larger than the volume")
+    pad = np.zeros(hr_shape, dtype=np.float64)
+    pad[: psf.shape[0], : psf.shape[1], : psf.shape[2]] = psf
+    pad = np.roll(pad, shift=tuple(-(k // 2) for k in psf.shape), axis=(0, 1, 2))
+    return _fftn(pad)
+
+
+def blur(x, otf):
+    """H x = F^H Lambda F x (eq. (2))."""
+    return np.real(_ifftn(otf * _fftn(x)))
+
+
+def blur_adjoint(x, otf):
+    """H^H x = F^H Lambda^H F x (eq. (2))."""
+    return np.real(_ifftn(np.conj(otf) * _fftn(x)))
+
+
+def decimate(z, rate):
+    """D: keep one voxel (offset 0) of every dr x dc x ds block."""
+    ds, dc, dr = _axes_rate(rate)
+    return z[::ds, ::dc, ::dr]
+
+
+def zero_fill(y, rate):
+    """D^H: interpolate with zeros, so that D D^H = I (Sec. II-A)."""
+    ds, dc, dr = _axes_rate(rate)
+    out = np.zeros(hr_shape_of(y.shape, rate), dtype=np.result_type(y, np.float64))
+    out[::ds, ::dc, ::dr] = y
+    return out
+
+
+def degrade(x, psf, rate):
+    """Noise-free part of eq. (1): D H x."""
+    return decimate(blur(np.asarray(x, np.float64), psf_to_otf(psf, x.shape)), rate)
+
+
+# ---------------------------------------------------------------------------
+# Decimation in the Fourier domain, eq. (8) and the definition of underline-Lambda
+# ---------------------------------------------------------------------------
+
+def fold(z, rate):
+    """[(1^T (x) I) (x) (1^T (x) I) (x) (1^T (x) I)] z: sum of every alias group.
+
+    An HR spectrum of shape (s_h, n_h, m_h) is viewed as
+    (ds, s_l, dc, n_l, dr, m_l); the Kronecker factor 1^T_{ds} (x) I_{s_l} sums
+    over the leading ds index, and likewise for n and m.
+    """
+    ds, dc, dr = _axes_rate(rate)
+    S, N, M = z.shape
+    v = z.reshape(ds, S // ds, dc, N // dc, dr, M // dr)
+    return v.sum(axis=(0, 2, 4))
+
+
+def unfold(z, rate):
+    """Adjoint of ``fold``: replicate an LR-sized array over the alias groups."""
+    ds, dc, dr = _axes_rate(rate)
+    return np.tile(z, (ds, dc, dr))
+
+
+# ---------------------------------------------------------------------------
+# Finite differences, Sec. III-B and Algorithm 1 steps 3-4
+# ---------------------------------------------------------------------------
+
+def diff_symbol_sq(shape):
+    """G = Sigma_h^H Sigma_h + Sigma_v^H Sigma_v + Sigma_s^H Sigma_s.
+
+    For a periodic forward difference along an axis of length n the symbol is
+    e^{2 pi i k / n} - 1, whose squared modulus is 4 sin^2(pi k / n).
+    Gamma of Algorithm 1 step 4 is 1/G (unbounded at k = 0).
+    """
+    S, N, M = shape
+    gs = 4.0 * np.sin(np.pi * np.arange(S) / S) ** 2
+    gn = 4.0 * np.sin(np.pi * np.arange(N) / N) ** 2
+    gm = 4.0 * np.sin(np.pi * np.arange(M) / M) ** 2
+    return gs[:, None, None] + gn[None, :, None] + gm[None, None, :]
+
+
+def grad(x):
+    """L x = [D_h x; D_v x; D_s x]: periodic forward differences.
+
+    Component 0 differences along m (array axis 2), 1 along n (axis 1),
+    2 along s (axis 0). (D_a x)[i] = x[i + e_a] - x[i].
+    """
+    return np.stack([np.roll(x, -1, axis=2) - x,
+                     np.roll(x, -1, axis=1) - x,
+                     np.roll(x, -1, axis=0) - x])
+
+
+def grad_adjoint(w):
+    """L^T w = sum_a D_a^T w_a with (D_a^T w)[i] = w[i - e_a] - w[i]."""
+    return ((np.roll(w[0], 1, axis=2) - w[0])
+            + (np.roll(w[1], 1, axis=1) - w[1])
+            + (np.roll(w[2], 1, axis=0) - w[2]))
+
+
+def shrink(nu, thr):
+    """Algorithm 1 step 5b: max{0, ||nu_j|| - thr} nu_j / ||nu_j|| per voxel j.
+
+    nu has shape (3, ...); the norm is over the 3 components. Where
+    ||nu_j|| = 0 the result is 0.
+    """
+    nrm = np.sqrt(np.sum(nu * nu, axis=0))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        scale = np.where(nrm > 0, np.maximum(0.0, nrm - thr) / nrm, 0.0)
+    return nu * scale[None]
+
+
+# ---------------------------------------------------------------------------
+# Tikhonov closed form, Sec. III-A, eq. (5)-(12)
+# ---------------------------------------------------------------------------
+
+def tikhonov(y, psf, rate, lam, xbar=None):
+    """3D-FSR-l2-l2: the minimiser of eq. (5) through eq. (12).
+
+    k = H^H D^H y + 2 lam xbar, so F k = conj(Lambda) F(D^H y) + 2 lam F xbar.
+    x = (1/2lam) k - (1/2lam) F^H Lbar^H (2 lam r I + Lbar Lbar^H)^{-1} Lbar F k,
+    where Lbar z = fold(Lambda z), Lbar^H w = conj(Lambda) unfold(w) and
+    Lbar Lbar^H = diag(fold(|Lambda|^2)).
+    """
+    y = np.asarray(y, np.float64)
+    hr = hr_shape_of(y.shape, rate)
+    otf = psf_to_otf(psf, hr)
+    d = int(np.prod(rate))
+    Fk = np.conj(otf) * _fftn(zero_fill(y, rate))
+    if xbar is not None:
+        Fk = Fk + 2.0 * lam * _fftn(np.asarray(xbar, np.float64))
+    t = fold(otf * Fk, rate) / (2.0 * lam * d + fold(np.abs(otf) ** 2, rate))
+    X = (Fk - np.conj(otf) * unfold(t, rate)) / (2.0 * lam)
+    return np.real(_ifftn(X))
+
+
+def tikhonov_objective(x, y, psf, rate, lam, xbar=None):
+    """Eq. (5): 1/2 ||y - D H x||^2 + lam ||x - xbar||^2."""
+    r = y - degrade(x, psf, rate)
+    dx = x if xbar is None else x - xbar
+    return 0.5 * float(np.sum(r * r)) + lam * float(np.sum(dx * dx))
+
+
+# ---------------------------------------------------------------------------
+# TV-ADMM, Sec. III-B, eq. (ADMM), Algorithm 1
+# ---------------------------------------------------------------------------
+
+def _dc_group_members(shape, rate):
+    """HR indices of the alias group containing k = 0: multiples of the LR size."""
+    ds, dc, dr = _axes_rate(rate)
+    S, N, M = shape
+    sl, nl, ml = S // ds, N // dc, M // dr
+    return [(c * sl, b * nl, a * ml)
+            for c in range(ds) for b in range(dc) for a in range(dr)]
+
+
+def x_update(Fk, otf, G, mu, rate):
+    """Algorithm 1 step 5a, in the Fourier domain.
+
+    x_f = Gamma Lbar^H (mu r I + Lbar Gamma Lbar^H)^{-1} Lbar Gamma Fk and
+    X = (Gamma Fk - x_f) / mu, with Gamma = 1/G.
+
+    Gamma is unbounded at k = 0, so the alias group containing k = 0 is solved
+    instead from its own normal equations (the Fourier form of
+    (H^T Dbar H + mu L^T L) X = Fk restricted to that group):
+        sum_b conj(L_a) L_b X_b / d + mu G_a X_a = Fk_a   for every member a,
+    by numpy.linalg.solve. Returns the full HR spectrum X.
+    """
+    d = int(np.prod(rate))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Gam = np.where(G > 0, 1.0 / np.where(G > 0, G, 1.0), 0.0)
+    num = fold(otf * Gam * Fk, rate)
+    den = mu * d + fold(np.abs(otf) ** 2 * Gam, rate)
+    xf = Gam * np.conj(otf) * unfold(num / den, rate)
+    X = (Gam * Fk - xf) / mu
+
+    idx = _dc_group_members(Fk.shape, rate)
+    lam_v = np.array([otf[i] for i in idx])
+    g_v = np.array([G[i] for i in idx])
+    b_v = np.array([Fk[i] for i in idx])
+    if abs(lam_v[0]) == 0.0:
+        raise ZeroDivisionError("Lambda(0) = 0: TV x-update is singular")
+    Mdc = np.outer(np.conj(lam_v), lam_v) / d + mu * np.diag(g_v)
+    x_v = np.linalg.solve(Mdc, b_v)
+    for i, v in zip(idx, x_v):
+        X[i] = v
+    return X
+
+
+def data_term(x, y, otf, rate):
+    """1/2 ||y - D H x||^2."""
+    r = y - decimate(blur(x, otf), rate)
+    return 0.5 * float(np.sum(r * r))
+
+
+def tv_objective(x, y, psf, rate, lam):
+    """Eq. (3) with isotropic TV: 1/2||y - DHx||^2 + lam sum_j ||(Lx)_j||_2."""
+    otf = psf_to_otf(psf, x.shape)
+    g = grad(x)
+    return data_term(x, y, otf, rate) + lam * float(np.sum(np.sqrt(np.sum(g * g, axis=0))))
+
+
+@dataclass
+class AdmmResult:
+    x: np.ndarray
+    u: np.ndarray
+    d: np.ndarray
+    iters: int
+    converged: bool
+    primal_rel: float
+    dual_rel: float
+    history: list = field(default_factory=list)
+
+
+def _rel(num, den):
+    return num / den if den > 0 else float("inf")
+
+
+def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
+            callback=None):
+    """3D-FSR-l2-TV (Algorithm 1).
+
+    Inputs y, H (through ``psf``), lam, r = prod(rate), mu.
+    Initialisation: x0 (zero if None); nu = L x0 (with d = 0), u0 = shrink(nu),
+    d0 = nu - u0, i.e. steps 5b/5c applied to x0.
+    Loop (until the stopping rule holds or ``max_iter`` iterations):
+      5a  rho = u - d; Theta = L^T rho; Fk = conj(Lambda) F D^H y + mu F Theta;
+          x = F^H X with X from ``x_update``.
+      5b  nu = L x + d; u' = shrink(nu, lam/mu).
+      5c  d' = d + (L x - u').
+    Stopping rule (tol > 0): ||L x - u'|| <= tol max(||L x||, ||u'||) and
+    mu ||L^T (u' - u)|| <= tol mu ||L^T d'||. tol = 0 runs exactly max_iter.
+    Output: x of the last x-update (step "Output").
+    """
+    y = np.asarray(y, np.float64)
+    hr = hr_shape_of(y.shape, rate)
+    otf = psf_to_otf(psf, hr)
+    G = diff_symbol_sq(hr)
+    FDty = np.conj(otf) * _fftn(zero_fill(y, rate))
+    thr = lam / mu
+
+    x = np.zeros(hr) if x0 is None else np.asarray(x0, np.float64).copy()
+    nu = grad(x)
+    u = shrink(nu, thr)
+    d = nu - u
+
+    hist = []
+    it = 0
+    converged = False
+    prel = drel = float("inf")
+    for it in range(1, max_iter + 1):
+        rho = u - d
+        theta = grad_adjoint(rho)
+        Fk = FDty + mu * _fftn(theta)
+        x = np.real(_ifftn(x_update(Fk, otf, G, mu, rate)))
+        Lx = grad(x)
+        nu = Lx + d
+        u_new = shrink(nu, thr)
+        d_new = d + (Lx - u_new)
+
+        r_norm = float(np.sqrt(np.sum((Lx - u_new) ** 2)))
+        s_norm = mu * float(np.sqrt(np.sum(grad_adjoint(u_new - u) ** 2)))
+        pri_den = max(float(np.sqrt(np.sum(Lx * Lx))), float(np.sqrt(np.sum(u_new * u_new))))
+        dual_den = mu * float(np.sqrt(np.sum(grad_adjoint(d_new) ** 2)))
+        prel, drel = _rel(r_norm, pri_den), _rel(s_norm, dual_den)
+        if record:
+            hist.append((prel, drel))
+        if callback is not None:
+            callback(it, x, u, d, u_new, d_new)
+        u, d = u_new, d_new
+        if tol > 0 and prel <= tol and drel <= tol:
+            converged = True
+            break
+    return AdmmResult(x=x, u=u, d=d, iters=it, converged=converged,
+                      primal_rel=prel, dual_rel=drel, history=hist)
+
+
+# ---------------------------------------------------------------------------
+# Metrics
+# ---------------------------------------------------------------------------
+
+def psnr(x, ref):
+    """Peak signal-to-noise ratio in dB, peak = max |ref|."""
+    mse = float(np.mean((np.asarray(x, np.float64) - ref) ** 2))
+    peak = float(np.max(np.abs(ref)))
+    return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
+
+
+def rel_l2(a, b):
+    """||a - b|| / ||b|| in float64."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = float(np.linalg.norm(b.ravel()))
+    return float(np.linalg.norm((a - b).ravel())) / (nb if nb > 0 else 1.0)
