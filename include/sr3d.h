@@ -1,0 +1,155 @@
+/*
+ * sr3d.h -- C ABI of libsr3d, an MI355X (gfx950) implementation of the fast
+ * Fourier-domain 3D single-image super-resolution solvers of Tuador et al.,
+ * "A Novel Fast 3D Single Image Super-Resolution Algorithm" (arXiv 2010.15491).
+ *
+ * Problem (Sec. II-A, eq. (1)):  y = D H x + n
+ *   x  HR volume of m_h x n_h x s_h voxels, y LR volume of m_l x n_l x s_l,
+ *   H  circular blur by a PSF (eq. (2)), D decimation by d = dr*dc*ds keeping
+ *      voxel offset 0 of every dr x dc x ds block.
+ *
+ * Memory layout of every volume: C order [s][n][m], m (rows) fastest -- the
+ * lexicographic order of Sec. II-A. A PSF of Km x Kn x Ks taps is [Ks][Kn][Km];
+ * its centre tap (K/2 per axis, integer division) is the origin of the
+ * circular convolution. Half spectra (R2C output) are [s][n][m/2+1] complex
+ * (interleaved float re, im), unnormalised.
+ *
+ * Ownership: the caller owns every pointer passed in (device memory unless
+ * stated) and the workspace. The library owns only per-device twiddle tables
+ * and a small pinned host block, created on first use and released by
+ * sr3d_shutdown(). Inputs are read-only; outputs must not alias inputs.
+ *
+ * Streams: all work is enqueued on the caller's stream. Functions return
+ * after enqueueing, except sr3d_tv_admm / sr3d_batch, which synchronise the
+ * stream to run the host stopping test and to fill `stats`.
+ *
+ * Errors: every function returns an sr3d_status. Argument errors are detected
+ * on the host before any HIP call. Errors found on the device (Lambda(0) = 0
+ * in a TV solve, a non-finite residual) are reported by sr3d_tv_admm /
+ * sr3d_batch after their final synchronisation. sr3d_last_error() gives a
+ * message for the calling thread's last failure.
+ */
+#ifndef SR3D_H
+#define SR3D_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SR3D_OK = 0,
+  SR3D_ERR_INVALID_ARG = -1,    /* NULL pointer, lambda/mu <= 0, tol < 0, max_iter < 1, rate < 1 */
+  SR3D_ERR_NOT_DIVISIBLE = -2,  /* an HR dimension is not a multiple of its rate */
+  SR3D_ERR_PSF_TOO_LARGE = -3,  /* a PSF extent exceeds the HR extent */
+  SR3D_ERR_UNSUPPORTED_SIZE = -4, /* an FFT length (HR or LR) outside the supported set */
+  SR3D_ERR_WORKSPACE = -5,      /* ws NULL or ws_bytes below sr3d_workspace_size() */
+  SR3D_ERR_SINGULAR = -6,       /* Lambda(0) = 0: the TV x-update (Alg. 1 step 5a) is singular */
+  SR3D_ERR_NONFINITE = -7,      /* a residual reduction produced NaN/Inf */
+  SR3D_ERR_HIP = -8             /* a HIP runtime call failed (see sr3d_last_error) */
+} sr3d_status;
+
+typedef struct { int m, n, s; } sr3d_dims;   /* m fastest */
+typedef struct { int dr, dc, ds; } sr3d_rate; /* decimation along m, n, s */
+
+typedef struct {
+  int iters;          /* ADMM iterations run (x-updates) */
+  int converged;      /* 1 if the tolerance test held, 0 if max_iter was reached */
+  double primal_rel;  /* ||Lx - u|| / max(||Lx||, ||u||) after the last iteration */
+  double dual_rel;    /* mu ||L^T (u' - u)|| / (mu ||L^T d||) after the last iteration */
+  double objective;   /* 1/2 ||y - DHx||^2 + lambda * sum_j ||(Lx)_j||_2 of the output x */
+} sr3d_stats;
+
+/* One TV super-resolution problem (Algorithm 1 of the paper, Sec. III-B). */
+typedef struct {
+  sr3d_dims hr;        /* HR size (m_h, n_h, s_h) */
+  sr3d_rate rate;      /* (dr, dc, ds); LR size is hr / rate per axis */
+  const float *y;      /* device, LR volume [s_l][n_l][m_l] */
+  const float *psf;    /* device, PSF [Ks][Kn][Km] */
+  sr3d_dims psf_dims;  /* (Km, Kn, Ks), each <= the HR extent */
+  float lambda_tv;     /* lambda of eq. (3)/Algorithm 1 (TV weight), > 0 */
+  float mu;            /* ADMM penalty mu > 0 */
+  float tol;           /* relative primal/dual residual tolerance; 0 => run max_iter */
+  int max_iter;        /* iteration cap, >= 1 */
+  const float *x0;     /* device HR initial guess, or NULL for x0 = 0 */
+  float *x;            /* device HR output [s_h][n_h][m_h] */
+  float *state;        /* optional device buffer of 3*N_h floats, or NULL (see below) */
+} sr3d_problem;
+
+/* sr3d_problem.state: the ADMM state (u, d) is kept as nu = L x + d_prev
+ * (three planes [3][s][n][m], components along m, n, s), from which
+ * u = shrink(nu) and d = nu - u (Algorithm 1 steps 5b, 5c). If `state` is
+ * non-NULL the solver keeps nu there instead of in the workspace, so the
+ * final (u, d) can be read back; with SR3D_RESUME it also supplies the
+ * initial state and x0 is ignored (checkpoint / resume). */
+
+/* flags for sr3d_tv_admm / sr3d_batch */
+#define SR3D_FP64_REDUCE 0x1   /* residual/objective reductions and the stopping test in FP64 (else FP32) */
+#define SR3D_RESUME      0x2   /* start from problem.state (must be non-NULL) */
+#define SR3D_USE_GRAPH   0x4   /* replay captured iterations as a HIP graph */
+#define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
+
+/* operations for sr3d_workspace_size */
+#define SR3D_OP_TIKHONOV 1
+#define SR3D_OP_TV_ADMM  2
+#define SR3D_OP_BATCH    3
+#define SR3D_OP_DEGRADE  4
+#define SR3D_OP_FFT      5
+
+/* Workspace bytes needed by `op` for problem(s) p[0..count-1] (count = 1
+ * except for SR3D_OP_BATCH). Only hr, rate and psf_dims are read. Returns 0
+ * for invalid sizes. For SR3D_OP_FFT, p->hr gives the transform size. */
+size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count);
+
+/* 3D-FSR-l2-l2: x = argmin 1/2||y - DHx||^2 + lambda ||x - xbar||^2, the
+ * closed form of eq. (12) (Sec. III-A): one 3D R2C FFT, a pointwise solve per
+ * alias group (eq. (8)-(12)), one 3D C2R FFT.
+ *   y     device LR volume, xbar device HR volume or NULL (xbar = 0),
+ *   lambda > 0 (eq. (5)), x device HR output. */
+int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf,
+                  sr3d_dims psf_dims, const float *xbar, float lambda, float *x,
+                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* 3D-FSR-l2-TV: Algorithm 1 (Sec. III-B). Initialisation u0, d0 from x0 by
+ * steps 5b/5c with d = 0 (x0 = 0 gives u0 = d0 = 0). Each iteration runs the
+ * x-update 5a through eq. (12) in the Fourier domain (the zero-frequency alias
+ * group, where Gamma = 1/G is unbounded, by exact elimination), then 5b, 5c.
+ * Stops when ||Lx-u'|| <= tol max(||Lx||,||u'||) and
+ * mu||L^T(u'-u)|| <= tol mu||L^T d'||, or after max_iter iterations.
+ * `stats` (host) may be NULL. */
+int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats,
+                 void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Many independent TV problems p[0..count-1] of uneven sizes and rates,
+ * solved together: each stage of an iteration is one launch over all active
+ * volumes; converged volumes drop out on the device. stats: host array of
+ * `count` entries or NULL. */
+int sr3d_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats,
+               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Forward model of eq. (1) without noise: y = D H x (circular blur by the
+ * PSF, then decimation). x device HR, y device LR. */
+int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf,
+                 sr3d_dims psf_dims, float *y, void *ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+/* Unnormalised 3D R2C DFT of a real volume [s][n][m] into its half spectrum
+ * [s][n][m/2+1] (complex interleaved), and the inverse C2R (scaled by 1/N, so
+ * that sr3d_irfft3d(sr3d_rfft3d(v)) = v). The inverse overwrites `spec`. */
+int sr3d_rfft3d(sr3d_dims dims, const float *in, float *spec, hipStream_t stream);
+int sr3d_irfft3d(sr3d_dims dims, float *spec, float *out, hipStream_t stream);
+
+/* Human-readable name of a status code. */
+const char *sr3d_status_string(int status);
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *sr3d_last_error(void);
+/* Releases twiddle tables and host staging on every device used. */
+void sr3d_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SR3D_H */

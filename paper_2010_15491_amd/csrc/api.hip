@@ -1,0 +1,451 @@
+// C ABI of libsr3d: argument checks, workspace layout and the host sequence
+// of kernel launches for the Tikhonov closed form (eq. (12)) and TV-ADMM
+// (Algorithm 1).
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sr3d_internal.h"
+
+namespace sr3d {
+void release_device_tables();
+thread_local std::string g_err;
+}  // namespace sr3d
+
+using namespace sr3d;
+
+namespace {
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return SR3D_ERR_HIP;
+}
+
+#define SR3D_TRY(expr, where)                     \
+  do {                                            \
+    hipError_t _e = (expr);                       \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+bool fold_d_supported(int d) {
+  switch (d) {
+    case 1: case 2: case 3: case 4: case 6: case 8: case 9: case 12: case 16: case 18: case 24:
+    case 27: case 32: case 36: case 48: case 64:
+      return true;
+    default:
+      return false;
+  }
+}
+
+struct Geometry {
+  int S, N, M, Sl, Nl, Ml, Mh, Mlh, D;
+  int dr, dc, ds;
+  long NH, NL, nspec, nlspec;
+};
+
+int check_geometry(sr3d_dims hr, sr3d_rate rate, const sr3d_dims *psf, Geometry *g) {
+  if (hr.m < 1 || hr.n < 1 || hr.s < 1) return fail(SR3D_ERR_INVALID_ARG, "HR dimensions must be >= 1");
+  if (rate.dr < 1 || rate.dc < 1 || rate.ds < 1) return fail(SR3D_ERR_INVALID_ARG, "rates must be >= 1");
+  if (hr.m % rate.dr || hr.n % rate.dc || hr.s % rate.ds)
+    return fail(SR3D_ERR_NOT_DIVISIBLE, "HR dimension not divisible by its decimation rate");
+  const long nh = (long)hr.m * hr.n * hr.s;
+  if (nh >= (1L << 31)) return fail(SR3D_ERR_UNSUPPORTED_SIZE, "volume has 2^31 or more voxels");
+  g->M = hr.m; g->N = hr.n; g->S = hr.s;
+  g->dr = rate.dr; g->dc = rate.dc; g->ds = rate.ds;
+  g->Ml = hr.m / rate.dr; g->Nl = hr.n / rate.dc; g->Sl = hr.s / rate.ds;
+  g->Mh = g->M / 2 + 1; g->Mlh = g->Ml / 2 + 1;
+  g->D = rate.dr * rate.dc * rate.ds;
+  g->NH = nh;
+  g->NL = (long)g->Ml * g->Nl * g->Sl;
+  g->nspec = (long)g->S * g->N * g->Mh;
+  g->nlspec = (long)g->Sl * g->Nl * g->Mlh;
+  const int lens[6] = {g->M, g->N, g->S, g->Ml, g->Nl, g->Sl};
+  for (int L : lens)
+    if (!fft_len_supported(L))
+      return fail(SR3D_ERR_UNSUPPORTED_SIZE,
+                  "FFT length " + std::to_string(L) + " not supported (1, 2^a or 3*2^a, <= 1024)");
+  if (!fold_d_supported(g->D))
+    return fail(SR3D_ERR_UNSUPPORTED_SIZE, "decimation factor d = dr*dc*ds not supported");
+  if (psf) {
+    if (psf->m < 1 || psf->n < 1 || psf->s < 1) return fail(SR3D_ERR_INVALID_ARG, "PSF dimensions must be >= 1");
+    if (psf->m > hr.m || psf->n > hr.n || psf->s > hr.s)
+      return fail(SR3D_ERR_PSF_TOO_LARGE, "PSF larger than the HR volume");
+  }
+  return SR3D_OK;
+}
+
+struct Carve {
+  char *base;
+  size_t off;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct TvWs {
+  Ctrl *ctrl;
+  void *partA, *partB, *partF;
+  float *g;
+  float2 *lam, *yh, *w, *w2;
+  float *nu, *theta, *ltu;
+  int nbA, nbF;
+};
+
+size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
+  Carve c{base, 0};
+  L->nbA = stencil_blocks(g.S, g.N, g.M);
+  FoldArgs fa{};
+  fa.Sl = g.Sl; fa.Nl = g.Nl; fa.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
+  L->nbF = fold_blocks(fa);
+  L->ctrl = c.take<Ctrl>(1);
+  L->partA = c.take<double>((size_t)4 * L->nbA);
+  L->partB = c.take<double>((size_t)2 * L->nbA);
+  L->partF = c.take<double>((size_t)L->nbF);
+  L->g = c.take<float>((size_t)g.M + g.N + g.S);
+  L->lam = c.take<float2>(g.nspec);
+  L->yh = c.take<float2>(g.nlspec);
+  L->w = c.take<float2>(g.nspec);
+  L->w2 = c.take<float2>(g.nspec);
+  L->nu = c.take<float>((size_t)3 * g.NH);
+  L->theta = c.take<float>(g.NH);
+  L->ltu = c.take<float>(g.NH);
+  return c.off + 256;
+}
+
+struct TikWs {
+  float2 *lam, *yh, *w, *w2;
+  float *real;
+};
+
+size_t tik_layout(const Geometry &g, char *base, TikWs *L) {
+  Carve c{base, 0};
+  L->lam = c.take<float2>(g.nspec);
+  L->yh = c.take<float2>(g.nlspec);
+  L->w = c.take<float2>(g.nspec);
+  L->w2 = c.take<float2>(g.nspec);
+  L->real = c.take<float>(g.NH);
+  return c.off + 256;
+}
+
+size_t degrade_layout(const Geometry &g, char *base, TikWs *L) {
+  Carve c{base, 0};
+  L->lam = c.take<float2>(g.nspec);
+  L->w = c.take<float2>(g.nspec);
+  L->real = c.take<float>(g.NH);
+  L->yh = nullptr;
+  L->w2 = nullptr;
+  return c.off + 256;
+}
+
+FoldArgs make_fold(const Geometry &g) {
+  FoldArgs a{};
+  a.S = g.S; a.N = g.N; a.M = g.M; a.Mh = g.Mh;
+  a.Sl = g.Sl; a.Nl = g.Nl; a.Ml = g.Ml; a.Mlh = g.Mlh;
+  a.dr = g.dr; a.dc = g.dc; a.ds = g.ds;
+  a.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
+  a.scale = (float)(1.0 / (double)g.NH);
+  return a;
+}
+
+// pinned host copies of the control block, one per calling thread
+std::mutex g_host_mu;
+std::vector<Ctrl *> g_host_blocks;
+thread_local Ctrl *t_host_ctrl = nullptr;
+
+Ctrl *host_ctrl() {
+  if (!t_host_ctrl) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sizeof(Ctrl) * 64, hipHostMallocDefault) != hipSuccess) return nullptr;
+    t_host_ctrl = reinterpret_cast<Ctrl *>(p);
+    std::lock_guard<std::mutex> lk(g_host_mu);
+    g_host_blocks.push_back(t_host_ctrl);
+  }
+  return t_host_ctrl;
+}
+
+int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
+  if (!p) return fail(SR3D_ERR_INVALID_ARG, "problem is NULL");
+  int rc = check_geometry(p->hr, p->rate, &p->psf_dims, g);
+  if (rc) return rc;
+  if (!p->y || !p->psf || !p->x) return fail(SR3D_ERR_INVALID_ARG, "y, psf and x must be non-NULL");
+  if (!(p->lambda_tv > 0.f) || !(p->mu > 0.f) || !isfinite(p->lambda_tv) || !isfinite(p->mu))
+    return fail(SR3D_ERR_INVALID_ARG, "lambda_tv and mu must be finite and > 0");
+  if (!(p->tol >= 0.f) || !isfinite(p->tol)) return fail(SR3D_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (p->max_iter < 1) return fail(SR3D_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if ((flags & SR3D_RESUME) && !p->state) return fail(SR3D_ERR_INVALID_ARG, "SR3D_RESUME needs problem.state");
+  if (p->x == p->y || p->x == p->psf) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
+  return SR3D_OK;
+}
+
+// Enqueue setup and initial state for one TV problem.
+hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu, int flags,
+                    bool fp64, hipStream_t st) {
+  hipError_t e;
+  if ((e = ctrl_init(L.ctrl, p->max_iter, p->tol, p->mu, p->lambda_tv, 1.0 / (double)g.NL, st))) return e;
+  if ((e = pad_psf(p->psf, p->psf_dims.s, p->psf_dims.n, p->psf_dims.m, L.theta, g.S, g.N, g.M, st))) return e;
+  if ((e = fft3d_forward(L.theta, L.lam, g.S, g.N, g.M, nullptr, st))) return e;
+  if ((e = fft3d_forward(p->y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st))) return e;
+  if ((e = diff_tables(L.g, g.S, g.N, g.M, st))) return e;
+  StencilArgs sa{};
+  sa.x = p->x0; sa.nu = nu; sa.theta = L.theta; sa.ltu = L.ltu;
+  sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
+  sa.partA = L.partA; sa.partB = L.partB; sa.done = nullptr;
+  if (!(flags & SR3D_RESUME)) {
+    if ((e = stencil_a(sa, p->x0 ? 1 : 2, fp64, st))) return e;
+  }
+  return stencil_b(sa, 1, fp64, st);
+}
+
+hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu, bool fp64,
+                        hipStream_t st) {
+  const int *done = &L.ctrl->done;
+  hipError_t e;
+  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+  FoldArgs fa = make_fold(g);
+  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+  fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+  fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 1;
+  fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+  if ((e = fold_solve(fa, fp64, st))) return e;
+  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  StencilArgs sa{};
+  sa.x = p->x; sa.nu = nu; sa.theta = L.theta; sa.ltu = L.ltu;
+  sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
+  sa.partA = L.partA; sa.partB = L.partB; sa.done = done;
+  if ((e = stencil_a(sa, 0, fp64, st))) return e;
+  if ((e = stencil_b(sa, 0, fp64, st))) return e;
+  return reduce_and_test(L.ctrl, L.partA, L.nbA, L.partB, L.nbA, L.partF, L.nbF, fp64, st);
+}
+
+int check_interval(int flags) {
+  const int k = (flags >> 8) & 0xff;
+  return k > 0 ? k : 8;
+}
+
+int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t ws_bytes,
+           hipStream_t st) {
+  Geometry g;
+  int rc = check_problem(p, flags, &g);
+  if (rc) return rc;
+  TvWs L;
+  const size_t need = tv_layout(g, nullptr, &L);
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  tv_layout(g, reinterpret_cast<char *>(ws), &L);
+  Ctrl *hc = host_ctrl();
+  if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  const bool fp64 = (flags & SR3D_FP64_REDUCE) != 0;
+  float *nu = p->state ? p->state : L.nu;
+  SR3D_TRY(tv_setup(g, L, p, nu, flags, fp64, st), "tv setup");
+  const int K = check_interval(flags);
+  if (flags & SR3D_USE_GRAPH) {
+    // Capture K iterations once on a private stream, replay until done.
+    hipStream_t cs;
+    SR3D_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream create");
+    hipEvent_t ev;
+    SR3D_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; e == hipSuccess && i < K; ++i) e = tv_iteration(g, L, p, nu, fp64, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+    for (int it = 0; e == hipSuccess && it < p->max_iter; it += K) {
+      e = hipGraphLaunch(exec, cs);
+      if (e == hipSuccess) e = hipMemcpyAsync(hc, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipStreamSynchronize(cs);
+      if (e == hipSuccess && hc->done) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipEventRecord(ev, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    (void)hipStreamSynchronize(cs);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "graph replay");
+  } else {
+    for (int it = 0; it < p->max_iter;) {
+      const int n = (p->max_iter - it) < K ? (p->max_iter - it) : K;
+      for (int i = 0; i < n; ++i) SR3D_TRY(tv_iteration(g, L, p, nu, fp64, st), "tv iteration");
+      it += n;
+      SR3D_TRY(hipMemcpyAsync(hc, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
+      SR3D_TRY(hipStreamSynchronize(st), "stream sync");
+      if (hc->done) break;
+    }
+  }
+  if (stats) {
+    stats->iters = hc->iter;
+    stats->converged = hc->converged;
+    stats->primal_rel = hc->primal_rel;
+    stats->dual_rel = hc->dual_rel;
+    stats->objective = hc->objective;
+  }
+  if (hc->status) {
+    return fail(hc->status, hc->status == SR3D_ERR_SINGULAR ? "Lambda(0) = 0: TV x-update singular"
+                                                            : "non-finite residual");
+  }
+  return SR3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
+  if (!p || count < 1) return 0;
+  Geometry g;
+  size_t total = 0;
+  const int n = (op == SR3D_OP_BATCH) ? count : 1;
+  for (int i = 0; i < n; ++i) {
+    const sr3d_dims *psf = (op == SR3D_OP_FFT) ? nullptr : &p[i].psf_dims;
+    sr3d_rate r = p[i].rate;
+    if (op == SR3D_OP_FFT) r = sr3d_rate{1, 1, 1};
+    if (check_geometry(p[i].hr, r, psf, &g) != SR3D_OK) return 0;
+    TvWs tv;
+    TikWs tk;
+    size_t b = 0;
+    switch (op) {
+      case SR3D_OP_TIKHONOV: b = tik_layout(g, nullptr, &tk); break;
+      case SR3D_OP_TV_ADMM:
+      case SR3D_OP_BATCH: b = tv_layout(g, nullptr, &tv); break;
+      case SR3D_OP_DEGRADE: b = degrade_layout(g, nullptr, &tk); break;
+      case SR3D_OP_FFT: b = 0; break;
+      default: return 0;
+    }
+    if (op == SR3D_OP_BATCH) total = b > total ? b : total;
+    else total += b;
+  }
+  return total;
+}
+
+int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf, sr3d_dims psf_dims,
+                  const float *xbar, float lambda, float *x, void *ws, size_t ws_bytes,
+                  hipStream_t st) {
+  Geometry g;
+  int rc = check_geometry(hr, rate, &psf_dims, &g);
+  if (rc) return rc;
+  if (!y || !psf || !x) return fail(SR3D_ERR_INVALID_ARG, "y, psf and x must be non-NULL");
+  if (!(lambda > 0.f) || !isfinite(lambda)) return fail(SR3D_ERR_INVALID_ARG, "lambda must be finite and > 0");
+  if (x == y || x == psf || (xbar && x == xbar)) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
+  TikWs L;
+  const size_t need = tik_layout(g, nullptr, &L);
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  tik_layout(g, reinterpret_cast<char *>(ws), &L);
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(pad_psf(psf, psf_dims.s, psf_dims.n, psf_dims.m, L.real, g.S, g.N, g.M, st), "pad psf");
+  SR3D_TRY(fft3d_forward(L.real, L.lam, g.S, g.N, g.M, nullptr, st), "fft Lambda");
+  SR3D_TRY(fft3d_forward(y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st), "fft y");
+  if (xbar) SR3D_TRY(fft3d_forward(xbar, L.w, g.S, g.N, g.M, nullptr, st), "fft xbar");
+  FoldArgs fa = make_fold(g);
+  fa.W = xbar ? L.w : nullptr; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+  fa.cw = 2.0f * lambda; fa.coefA = 2.0f * lambda; fa.tv = 0;
+  fa.partial = nullptr; fa.ctrl = nullptr; fa.done = nullptr;
+  SR3D_TRY(fold_solve(fa, false, st), "fold solve");
+  SR3D_TRY(fft3d_inverse(L.w2, x, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
+  return SR3D_OK;
+}
+
+int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t ws_bytes,
+                 hipStream_t st) {
+  return run_tv(p, flags, stats, ws, ws_bytes, st);
+}
+
+int sr3d_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
+               size_t ws_bytes, hipStream_t st) {
+  if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
+  Geometry g;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_problem(&p[i], flags, &g);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < count; ++i) {
+    int rc = run_tv(&p[i], flags, stats ? &stats[i] : nullptr, ws, ws_bytes, st);
+    if (rc) return rc;
+  }
+  return SR3D_OK;
+}
+
+int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf, sr3d_dims psf_dims,
+                 float *y, void *ws, size_t ws_bytes, hipStream_t st) {
+  Geometry g;
+  int rc = check_geometry(hr, rate, &psf_dims, &g);
+  if (rc) return rc;
+  if (!x || !psf || !y) return fail(SR3D_ERR_INVALID_ARG, "x, psf and y must be non-NULL");
+  TikWs L;
+  const size_t need = degrade_layout(g, nullptr, &L);
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  degrade_layout(g, reinterpret_cast<char *>(ws), &L);
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(pad_psf(psf, psf_dims.s, psf_dims.n, psf_dims.m, L.real, g.S, g.N, g.M, st), "pad psf");
+  SR3D_TRY(fft3d_forward(L.real, L.lam, g.S, g.N, g.M, nullptr, st), "fft Lambda");
+  SR3D_TRY(fft3d_forward(x, L.w, g.S, g.N, g.M, nullptr, st), "fft x");
+  SR3D_TRY(spectrum_mul(L.w, L.lam, (size_t)g.nspec, (float)(1.0 / (double)g.NH), st), "multiply");
+  SR3D_TRY(fft3d_inverse(L.w, L.real, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
+  SR3D_TRY(decimate(L.real, y, g.S, g.N, g.M, g.dr, g.dc, g.ds, st), "decimate");
+  return SR3D_OK;
+}
+
+int sr3d_rfft3d(sr3d_dims d, const float *in, float *spec, hipStream_t st) {
+  Geometry g;
+  int rc = check_geometry(d, sr3d_rate{1, 1, 1}, nullptr, &g);
+  if (rc) return rc;
+  if (!in || !spec) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(fft3d_forward(in, reinterpret_cast<float2 *>(spec), g.S, g.N, g.M, nullptr, st), "rfft3d");
+  return SR3D_OK;
+}
+
+int sr3d_irfft3d(sr3d_dims d, float *spec, float *out, hipStream_t st) {
+  Geometry g;
+  int rc = check_geometry(d, sr3d_rate{1, 1, 1}, nullptr, &g);
+  if (rc) return rc;
+  if (!spec || !out) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(fft3d_inverse(reinterpret_cast<float2 *>(spec), out, g.S, g.N, g.M,
+                         (float)(1.0 / (double)g.NH), nullptr, st),
+           "irfft3d");
+  return SR3D_OK;
+}
+
+const char *sr3d_status_string(int s) {
+  switch (s) {
+    case SR3D_OK: return "SR3D_OK";
+    case SR3D_ERR_INVALID_ARG: return "SR3D_ERR_INVALID_ARG";
+    case SR3D_ERR_NOT_DIVISIBLE: return "SR3D_ERR_NOT_DIVISIBLE";
+    case SR3D_ERR_PSF_TOO_LARGE: return "SR3D_ERR_PSF_TOO_LARGE";
+    case SR3D_ERR_UNSUPPORTED_SIZE: return "SR3D_ERR_UNSUPPORTED_SIZE";
+    case SR3D_ERR_WORKSPACE: return "SR3D_ERR_WORKSPACE";
+    case SR3D_ERR_SINGULAR: return "SR3D_ERR_SINGULAR";
+    case SR3D_ERR_NONFINITE: return "SR3D_ERR_NONFINITE";
+    case SR3D_ERR_HIP: return "SR3D_ERR_HIP";
+    default: return "SR3D_ERR_UNKNOWN";
+  }
+}
+
+const char *sr3d_last_error(void) { return g_err.c_str(); }
+
+void sr3d_shutdown(void) {
+  release_device_tables();
+  std::lock_guard<std::mutex> lk(g_host_mu);
+  for (Ctrl *c : g_host_blocks) (void)hipHostFree(c);
+  g_host_blocks.clear();
+  t_host_ctrl = nullptr;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libsr3d (include/sr3d.h).
+
+Argument marshalling only: tensors are torch CUDA tensors (float32, C order
+(s, n, m)); their device pointers and the current stream are passed to the C
+ABI, where every step of the solvers runs in HIP kernels. There is no CPU
+fallback: loading fails loudly if libsr3d.so is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsr3d.so")
+
+SR3D_OK = 0
+STATUS = {0: "SR3D_OK", -1: "SR3D_ERR_INVALID_ARG", -2: "SR3D_ERR_NOT_DIVISIBLE",
+          -3: "SR3D_ERR_PSF_TOO_LARGE", -4: "SR3D_ERR_UNSUPPORTED_SIZE",
+          -5: "SR3D_ERR_WORKSPACE", -6: "SR3D_ERR_SINGULAR", -7: "SR3D_ERR_NONFINITE",
+          -8: "SR3D_ERR_HIP"}
+
+FP64_REDUCE = 0x1
+RESUME = 0x2
+USE_GRAPH = 0x4
+
+
+def CHECK_INTERVAL(k):
+    return (int(k) & 0xFF) << 8
+
+
+OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
+
+EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
+           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_status_string",
+           "sr3d_last_error", "sr3d_shutdown"]
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("s", ctypes.c_int)]
+
+
+class Rate(ctypes.Structure):
+    _fields_ = [("dr", ctypes.c_int), ("dc", ctypes.c_int), ("ds", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
+                ("primal_rel", ctypes.c_double), ("dual_rel", ctypes.c_double),
+                ("objective", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("hr", Dims), ("rate", Rate), ("y", ctypes.c_void_p), ("psf", ctypes.c_void_p),
+                ("psf_dims", Dims), ("lambda_tv", ctypes.c_float), ("mu", ctypes.c_float),
+                ("tol", ctypes.c_float), ("max_iter", ctypes.c_int), ("x0", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("state", ctypes.c_void_p)]
+
+
+class Sr3dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libsr3d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run paper_2010_15491_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, sz, ci, cf = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float
+        lib.sr3d_workspace_size.argtypes = [ci, ctypes.POINTER(Problem), ci]
+        lib.sr3d_workspace_size.restype = sz
+        lib.sr3d_tikhonov.argtypes = [Dims, Rate, vp, vp, Dims, vp, cf, vp, vp, sz, vp]
+        lib.sr3d_tikhonov.restype = ci
+        lib.sr3d_tv_admm.argtypes = [ctypes.POINTER(Problem), ci, ctypes.POINTER(Stats), vp, sz, vp]
+        lib.sr3d_tv_admm.restype = ci
+        lib.sr3d_batch.argtypes = [ctypes.POINTER(Problem), ci, ci, ctypes.POINTER(Stats), vp, sz, vp]
+        lib.sr3d_batch.restype = ci
+        lib.sr3d_degrade.argtypes = [Dims, Rate, vp, vp, Dims, vp, vp, sz, vp]
+        lib.sr3d_degrade.restype = ci
+        lib.sr3d_rfft3d.argtypes = [Dims, vp, vp, vp]
+        lib.sr3d_rfft3d.restype = ci
+        lib.sr3d_irfft3d.argtypes = [Dims, vp, vp, vp]
+        lib.sr3d_irfft3d.restype = ci
+        lib.sr3d_status_string.argtypes = [ci]
+        lib.sr3d_status_string.restype = ctypes.c_char_p
+        lib.sr3d_last_error.argtypes = []
+        lib.sr3d_last_error.restype = ctypes.c_char_p
+        lib.sr3d_shutdown.argtypes = []
+        lib.sr3d_shutdown.restype = None
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != SR3D_OK:
+        raise Sr3dError(rc, load().sr3d_last_error().decode())
+
+
+def dims_of(shape):
+    """(s, n, m) array shape -> Dims(m, n, s)."""
+    s, n, m = (int(v) for v in shape)
+    return Dims(m, n, s)
+
+
+def rate_of(rate):
+    dr, dc, ds = (int(v) for v in rate)
+    return Rate(dr, dc, ds)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a CUDA float32 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def workspace_bytes(op, problems):
+    arr = (Problem * len(problems))(*problems)
+    return int(load().sr3d_workspace_size(op, arr, len(problems)))
+
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _problem(hr_shape, rate, psf, lam=1.0, mu=1.0, tol=0.0, max_iter=1, y=None, x=None, x0=None,
+             state=None):
+    return Problem(dims_of(hr_shape), rate_of(rate), _ptr(y), _ptr(psf), dims_of(psf.shape),
+                   float(lam), float(mu), float(tol), int(max_iter), _ptr(x0), _ptr(x), _ptr(state))
+
+
+def lr_shape(hr_shape, rate):
+    s, n, m = hr_shape
+    dr, dc, ds = rate
+    return (s // ds, n // dc, m // dr)
+
+
+def hr_shape(lr, rate):
+    s, n, m = lr
+    dr, dc, ds = rate
+    return (s * ds, n * dc, m * dr)
+
+
+def tikhonov(y, psf, rate, lam, xbar=None, out=None, stream=None):
+    """3D-FSR-l2-l2 (eq. (12)): returns x (HR, float32, on y's device)."""
+    import torch
+    _dev_f32(y, "y")
+    _dev_f32(psf, "psf")
+    if xbar is not None:
+        _dev_f32(xbar, "xbar")
+    hr = hr_shape(tuple(y.shape), rate)
+    x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=y.device)
+    p = _problem(hr, rate, psf)
+    ws = _workspace(workspace_bytes(OP_TIKHONOV, [p]), y.device)
+    _check(load().sr3d_tikhonov(dims_of(hr), rate_of(rate), _ptr(y), _ptr(psf), dims_of(psf.shape),
+                                _ptr(xbar), float(lam), _ptr(x), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return x
+
+
+@dataclass
+class AdmmStats:
+    iters: int
+    converged: bool
+    primal_rel: float
+    dual_rel: float
+    objective: float
+
+
+def _stats(s):
+    return AdmmStats(int(s.iters), bool(s.converged), float(s.primal_rel), float(s.dual_rel),
+                     float(s.objective))
+
+
+def tv_admm(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE, state=None,
+            out=None, workspace=None, stream=None):
+    """3D-FSR-l2-TV (Algorithm 1). Returns (x, AdmmStats)."""
+    import torch
+    _dev_f32(y, "y")
+    _dev_f32(psf, "psf")
+    if x0 is not None:
+        _dev_f32(x0, "x0")
+    if state is not None:
+        _dev_f32(state, "state")
+    hr = hr_shape(tuple(y.shape), rate)
+    x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=y.device)
+    p = _problem(hr, rate, psf, lam, mu, tol, max_iter, y=y, x=x, x0=x0, state=state)
+    need = workspace_bytes(OP_TV_ADMM, [p])
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, y.device)
+    st = Stats()
+    _check(load().sr3d_tv_admm(ctypes.byref(p), int(flags), ctypes.byref(st), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    return x, _stats(st)
+
+
+def batch(problems, flags=FP64_REDUCE, workspace=None, stream=None):
+    """Solve many TV problems. ``problems`` is a list of dicts with keys
+    y, psf, rate, lam, mu, max_iter, tol, and optional x0, x. Returns
+    (list of x, list of AdmmStats)."""
+    import torch
+    ps, xs = [], []
+    for q in problems:
+        y, psf = _dev_f32(q["y"], "y"), _dev_f32(q["psf"], "psf")
+        hr = hr_shape(tuple(y.shape), q["rate"])
+        x = q.get("x")
+        if x is None:
+            x = torch.empty(hr, dtype=torch.float32, device=y.device)
+        xs.append(x)
+        ps.append(_problem(hr, q["rate"], psf, q["lam"], q["mu"], q.get("tol", 0.0),
+                           q["max_iter"], y=y, x=x, x0=q.get("x0")))
+    arr = (Problem * len(ps))(*ps)
+    need = int(load().sr3d_workspace_size(OP_BATCH, arr, len(ps)))
+    dev = problems[0]["y"].device
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    sts = (Stats * len(ps))()
+    _check(load().sr3d_batch(arr, len(ps), int(flags), sts, _ptr(ws), ws.numel(), _stream(stream)))
+    return xs, [_stats(s) for s in sts]
+
+
+def degrade(x, psf, rate, stream=None):
+    """y = D H x (eq. (1) without noise)."""
+    import torch
+    _dev_f32(x, "x")
+    _dev_f32(psf, "psf")
+    hr = tuple(x.shape)
+    y = torch.empty(lr_shape(hr, rate), dtype=torch.float32, device=x.device)
+    p = _problem(hr, rate, psf)
+    ws = _workspace(workspace_bytes(OP_DEGRADE, [p]), x.device)
+    _check(load().sr3d_degrade(dims_of(hr), rate_of(rate), _ptr(x), _ptr(psf), dims_of(psf.shape),
+                               _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
+
+
+def rfft3d(x, stream=None):
+    """Unnormalised 3D R2C DFT: returns complex64 (s, n, m//2+1)."""
+    import torch
+    _dev_f32(x, "x")
+    s, n, m = x.shape
+    spec = torch.empty((s, n, m // 2 + 1, 2), dtype=torch.float32, device=x.device)
+    _check(load().sr3d_rfft3d(dims_of(x.shape), _ptr(x), _ptr(spec), _stream(stream)))
+    return torch.view_as_complex(spec)
+
+
+def irfft3d(spec, shape, stream=None):
+    """Inverse of rfft3d (scaled by 1/N). ``spec`` is consumed (overwritten)."""
+    import torch
+    sp = torch.view_as_real(spec)
+    if not sp.is_contiguous():
+        raise ValueError("spectrum must be contiguous")
+    out = torch.empty(tuple(shape), dtype=torch.float32, device=spec.device)
+    _check(load().sr3d_irfft3d(dims_of(shape), _ptr(sp), _ptr(out), _stream(stream)))
+    return out
+
+
+def shutdown():
+    load().sr3d_shutdown()

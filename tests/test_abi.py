@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/sr3d.h declares, and rejects bad arguments on the host before any HIP
+call (status codes of the header)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2010_15491_amd import sr3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sr3d.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sr3d_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(sr3d.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sr3d.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = sr3d.load()
+    for code, name in sr3d.STATUS.items():
+        assert lib.sr3d_status_string(code).decode() == name
+
+
+def _prob(hr=(32, 32, 32), rate=(2, 2, 2), psf=(5, 5, 5), lam=1e-3, mu=5e-2, tol=0.0, it=10,
+          ptr=1):
+    p = sr3d.Problem()
+    p.hr = sr3d.Dims(hr[2], hr[1], hr[0])
+    p.rate = sr3d.Rate(*rate)
+    p.psf_dims = sr3d.Dims(psf[2], psf[1], psf[0])
+    p.y, p.psf, p.x = (None, None, None) if ptr is None else (ptr, ptr + 8, ptr + 16)
+    p.lambda_tv, p.mu, p.tol, p.max_iter = lam, mu, tol, it
+    return p
+
+
+def test_workspace_size_query():
+    lib = sr3d.load()
+    p = _prob()
+    n_tik = lib.sr3d_workspace_size(sr3d.OP_TIKHONOV, ctypes.byref(p), 1)
+    n_tv = lib.sr3d_workspace_size(sr3d.OP_TV_ADMM, ctypes.byref(p), 1)
+    assert n_tik > 4 * 32 ** 3 and n_tv > n_tik
+    bad = _prob(hr=(30, 32, 32))
+    assert lib.sr3d_workspace_size(sr3d.OP_TV_ADMM, ctypes.byref(bad), 1) == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(hr=(32, 32, 33)), "SR3D_ERR_NOT_DIVISIBLE"),
+    (dict(hr=(40, 40, 40)), "SR3D_ERR_UNSUPPORTED_SIZE"),
+    (dict(hr=(32, 32, 2048), rate=(2, 2, 2)), "SR3D_ERR_UNSUPPORTED_SIZE"),
+    (dict(rate=(8, 8, 4)), "SR3D_ERR_UNSUPPORTED_SIZE"),
+    (dict(psf=(5, 5, 40)), "SR3D_ERR_PSF_TOO_LARGE"),
+    (dict(lam=0.0), "SR3D_ERR_INVALID_ARG"),
+    (dict(mu=-1.0), "SR3D_ERR_INVALID_ARG"),
+    (dict(tol=-1.0), "SR3D_ERR_INVALID_ARG"),
+    (dict(it=0), "SR3D_ERR_INVALID_ARG"),
+    (dict(rate=(0, 2, 2)), "SR3D_ERR_INVALID_ARG"),
+    (dict(ptr=None), "SR3D_ERR_INVALID_ARG"),
+    (dict(), "SR3D_ERR_WORKSPACE"),
+])
+def test_tv_admm_host_argument_errors(kw, code):
+    lib = sr3d.load()
+    p = _prob(**kw)
+    rc = lib.sr3d_tv_admm(ctypes.byref(p), 0, None, None, 0, None)
+    assert sr3d.STATUS[rc] == code
+    assert lib.sr3d_last_error().decode() != ""
+
+
+def test_tikhonov_host_argument_errors():
+    lib = sr3d.load()
+    d, r, k = sr3d.Dims(32, 32, 32), sr3d.Rate(2, 2, 2), sr3d.Dims(5, 5, 5)
+    assert lib.sr3d_tikhonov(d, r, 1, 1, k, None, 0.0, 2, None, 0, None) == -1
+    assert lib.sr3d_tikhonov(d, r, None, 1, k, None, 1e-3, 2, None, 0, None) == -1
+    assert lib.sr3d_tikhonov(d, r, 1, 1, k, None, 1e-3, 1, None, 0, None) == -1  # x aliases y
+    assert lib.sr3d_tikhonov(sr3d.Dims(32, 32, 31), r, 1, 1, k, None, 1e-3, 2, None, 0, None) == -2
+    assert lib.sr3d_tikhonov(d, r, 1, 1, k, None, 1e-3, 2, None, 0, None) == -5
+
+
+def test_batch_and_resume_host_errors():
+    lib = sr3d.load()
+    arr = (sr3d.Problem * 2)(_prob(), _prob(hr=(32, 32, 31)))
+    assert lib.sr3d_batch(arr, 2, 0, None, None, 0, None) == -2
+    assert lib.sr3d_batch(arr, 0, 0, None, None, 0, None) == -1
+    p = _prob()
+    assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.RESUME, None, None, 0, None) == -1
+
+
+def test_fft_host_errors():
+    lib = sr3d.load()
+    assert lib.sr3d_rfft3d(sr3d.Dims(40, 8, 8), 1, 2, None) == -4
+    assert lib.sr3d_rfft3d(sr3d.Dims(32, 8, 8), None, 2, None) == -1
+    assert lib.sr3d_irfft3d(sr3d.Dims(0, 8, 8), 1, 2, None) == -1

@@ -1,0 +1,289 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle, element by element.
+
+Inputs are seeded synthetic phantoms; both sides get the same float32-rounded
+y, PSF and x0. Bar for the FP32 path: rel-L2 <= 1e-5 against FP64.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_15491_amd import phantom, sr3d
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = 1e-5
+
+
+def dev(a):
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def problem(shape, rate, sigma, noise, seed, texture=False, n_ell=12):
+    p = phantom.make_problem(shape, rate, sigma, noise, seed, texture=texture, n_ellipsoids=n_ell)
+    psf = f32(p["psf"])
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    return y, psf, p["x_true"]
+
+
+# ---------------------------------------------------------------------------
+# FFT
+# ---------------------------------------------------------------------------
+
+LENGTHS = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+
+
+def fft_shapes():
+    out = []
+    for L in LENGTHS:
+        out += [(L, 3, 4), (3, L, 6), (4, 3, L)]
+    out += [(24, 48, 32), (8, 96, 64), (64, 64, 64), (16, 12, 2), (2, 768, 6), (1024, 2, 2)]
+    return out
+
+
+@pytest.mark.parametrize("shape", fft_shapes())
+def test_rfft3d_matches_numpy(shape):
+    rng = np.random.default_rng(sum(shape))
+    x = f32(rng.standard_normal(shape))
+    X = sr3d.rfft3d(dev(x))
+    ref = np.fft.rfftn(x)
+    got = X.cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 2e-6, (shape, err)
+    back = host(sr3d.irfft3d(X, shape))
+    assert np.linalg.norm(back - x) / np.linalg.norm(x) < 2e-6
+
+
+def test_rfft3d_matches_bruteforce_dft():
+    rng = np.random.default_rng(3)
+    shape = (3, 4, 6)
+    x = f32(rng.standard_normal(shape))
+    S, N, M = shape
+    s, n, m = np.meshgrid(np.arange(S), np.arange(N), np.arange(M), indexing="ij")
+    ref = np.zeros((S, N, M // 2 + 1), complex)
+    for ks in range(S):
+        for kn in range(N):
+            for km in range(M // 2 + 1):
+                ref[ks, kn, km] = np.sum(x * np.exp(-2j * np.pi * (ks * s / S + kn * n / N + km * m / M)))
+    got = sr3d.rfft3d(dev(x)).cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Forward model and Tikhonov (eq. (12))
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("shape,rate,kshape", [((32, 32, 32), (2, 2, 2), (5, 5, 5)),
+                                               ((16, 24, 48), (2, 3, 4), (3, 2, 5)),
+                                               ((8, 96, 64), (4, 4, 2), (5, 3, 3))])
+def test_degrade_matches_oracle(shape, rate, kshape):
+    rng = np.random.default_rng(7)
+    x = f32(rng.standard_normal(shape))
+    psf = f32(rng.uniform(0.1, 1, kshape))
+    psf /= psf.sum()
+    psf = f32(psf)
+    got = host(sr3d.degrade(dev(x), dev(psf), rate))
+    ref = O.degrade(x, psf, rate)
+    assert O.rel_l2(got, ref) < 2e-6
+
+
+def test_tikhonov_config_32cube():
+    """Plain Tikhonov closed form: 32^3, d = 2x2x2, PSF 5^3 sigma 1.0, noise 0.01, tau 1e-3."""
+    y, psf, _ = problem((32, 32, 32), (2, 2, 2), 1.0, 0.01, 0)
+    x = host(sr3d.tikhonov(dev(y), dev(psf), (2, 2, 2), 1e-3))
+    ref = O.tikhonov(y, psf, (2, 2, 2), 1e-3)
+    assert O.rel_l2(x, ref) < TOL
+
+
+@pytest.mark.parametrize("shape,rate,kshape,lam", [
+    ((32, 32, 32), (2, 2, 2), (3, 2, 5), 1e-3),
+    ((16, 24, 48), (2, 3, 4), (3, 3, 3), 5e-3),
+    ((48, 32, 24), (1, 1, 1), (5, 5, 5), 1e-2),
+    ((8, 96, 64), (4, 4, 2), (5, 3, 3), 1e-3),
+    ((64, 64, 32), (1, 2, 4), (7, 7, 7), 2e-3),
+    ((12, 6, 3), (3, 2, 1), (3, 3, 3), 1e-2),
+])
+def test_tikhonov_matches_oracle_with_xbar(shape, rate, kshape, lam):
+    rng = np.random.default_rng(11)
+    psf = f32(rng.uniform(0.05, 1, kshape))
+    psf = f32(psf / psf.sum())
+    x_true = rng.standard_normal(shape)
+    y = f32(O.degrade(x_true, psf, rate) + 0.01 * rng.standard_normal(O.lr_shape_of(shape, rate)))
+    xbar = f32(rng.standard_normal(shape) * 0.1)
+    got = host(sr3d.tikhonov(dev(y), dev(psf), rate, lam, xbar=dev(xbar)))
+    ref = O.tikhonov(y, psf, rate, lam, xbar)
+    assert O.rel_l2(got, ref) < TOL
+    got0 = host(sr3d.tikhonov(dev(y), dev(psf), rate, lam))
+    assert O.rel_l2(got0, O.tikhonov(y, psf, rate, lam)) < TOL
+
+
+# ---------------------------------------------------------------------------
+# TV-ADMM (Algorithm 1)
+# ---------------------------------------------------------------------------
+
+LAM_TV, MU = 2e-3, 5e-2
+
+
+@pytest.mark.parametrize("shape,rate,sigma,iters", [
+    ((32, 32, 32), (2, 2, 2), 1.5, 1),
+    ((32, 32, 32), (2, 2, 2), 1.5, 10),
+    ((64, 64, 64), (2, 2, 2), 1.5, 100),
+    ((32, 48, 64), (2, 2, 4), 1.2, 30),
+    ((64, 96, 96), (4, 4, 2), 1.0, 20),
+    ((24, 12, 16), (1, 1, 1), 1.0, 15),
+])
+def test_tv_admm_fixed_iterations_match_oracle(shape, rate, sigma, iters):
+    y, psf, _ = problem(shape, rate, sigma, 0.02, 1)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, iters)
+    x = host(x)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, iters)
+    assert st.iters == iters and not st.converged
+    err = O.rel_l2(x, ref.x)
+    print(f"{shape} {rate} {iters} it: rel-L2 {err:.3e}")
+    assert err < TOL
+    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-2)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=5e-2)
+
+
+def test_tv_admm_warm_start_x0_matches_oracle():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, x_true = problem(shape, rate, 1.5, 0.02, 5)
+    x0 = f32(O.tikhonov(y, psf, rate, 1e-3))
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 25, x0=dev(x0))
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 25, x0=x0)
+    assert O.rel_l2(host(x), ref.x) < TOL
+
+
+def test_tv_admm_tolerance_stop_matches_oracle():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 6)
+    tol = 2e-2
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 200, tol=tol)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 200, tol=tol)
+    assert ref.converged and st.converged
+    assert abs(st.iters - ref.iters) <= 1
+    assert st.primal_rel <= tol and st.dual_rel <= tol
+
+
+def test_tv_admm_objective_matches_oracle():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 7)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 12)
+    obj = O.tv_objective(host(x), y, psf, rate, LAM_TV)
+    assert np.isclose(st.objective, obj, rtol=1e-4)
+
+
+def test_tv_admm_state_invariants_and_resume():
+    """||d_j|| <= lam/mu with d = nu - shrink(nu); resuming from the state
+    continues the same iteration sequence."""
+    shape, rate = (32, 32, 64), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 8)
+    N = int(np.prod(shape))
+    state = torch.zeros(3 * N, device="cuda")
+    x10, _ = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10, state=state)
+    nu = host(state).reshape((3,) + shape)
+    u = O.shrink(nu, LAM_TV / MU)
+    d = nu - u
+    assert np.sqrt((d ** 2).sum(0)).max() <= (LAM_TV / MU) * (1 + 1e-5)
+    x20r, _ = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10, state=state,
+                           flags=sr3d.FP64_REDUCE | sr3d.RESUME)
+    x20, _ = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 20)
+    assert torch.equal(x20r, x20)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 20)
+    assert O.rel_l2(host(x20), ref.x) < TOL
+
+
+def test_fp32_and_fp64_reductions_leave_x_unchanged_and_graph_replay():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 9)
+    Y, P = dev(y), dev(psf)
+    xa, sa = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 17, flags=sr3d.FP64_REDUCE)
+    xb, sb = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 17, flags=0)
+    xc, sc = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 17,
+                          flags=sr3d.FP64_REDUCE | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(5))
+    assert torch.equal(xa, xb) and torch.equal(xa, xc)
+    assert sa.iters == sb.iters == sc.iters == 17
+    assert np.isclose(sa.primal_rel, sb.primal_rel, rtol=1e-3)
+
+
+def test_repeat_runs_are_bitwise_identical():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 10)
+    a, sa = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 9)
+    b, sb = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 9)
+    assert torch.equal(a, b) and sa.primal_rel == sb.primal_rel
+
+
+def test_singular_lambda0_is_reported():
+    shape, rate = (16, 16, 16), (2, 2, 2)
+    y = np.zeros(O.lr_shape_of(shape, rate))
+    psf = np.array([[[1.0, -1.0]]])  # sums to zero: Lambda(0) = 0
+    with pytest.raises(sr3d.Sr3dError) as e:
+        sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 3)
+    assert e.value.status == -6
+
+
+def test_nonfinite_input_is_reported():
+    shape, rate = (16, 16, 16), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.0, 0.02, 11, n_ell=3)
+    y[1, 2, 3] = np.nan
+    with pytest.raises(sr3d.Sr3dError) as e:
+        sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 3)
+    assert e.value.status == -7
+
+
+def test_batch_matches_single_solves():
+    cases = [((32, 32, 32), (2, 2, 2), 1.0), ((32, 48, 48), (4, 4, 2), 1.5),
+             ((16, 32, 32), (2, 2, 4), 0.8)]
+    probs, refs = [], []
+    for i, (shape, rate, sig) in enumerate(cases):
+        y, psf, _ = problem(shape, rate, sig, 0.02, 100 + i, n_ell=6)
+        probs.append(dict(y=dev(y), psf=dev(psf), rate=rate, lam=LAM_TV, mu=MU, max_iter=15,
+                          tol=0.0))
+        refs.append(O.admm_tv(y, psf, rate, LAM_TV, MU, 15).x)
+    xs, sts = sr3d.batch(probs)
+    for x, st, ref, q in zip(xs, sts, refs, probs):
+        single, _ = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 15)
+        assert st.iters == 15
+        assert O.rel_l2(host(x), host(single)) < 1e-6
+        assert O.rel_l2(host(x), ref) < TOL
+
+
+# ---------------------------------------------------------------------------
+# Full size (256^3, the benchmark workload): first iterate against the oracle,
+# invariants after the benchmark's iterations.
+# ---------------------------------------------------------------------------
+
+
+def test_full_size_256_first_iterations_and_invariants():
+    shape, rate = (256, 256, 256), (2, 2, 2)
+    p = phantom.make_problem(shape, rate, 1.5, 0.02, 1, texture=True)
+    psf = f32(p["psf"])
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    Y, P = dev(y), dev(psf)
+    x2, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 2)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 2)
+    err = O.rel_l2(host(x2), ref.x)
+    print(f"256^3 after 2 iterations: rel-L2 {err:.3e}")
+    assert err < TOL
+    state = torch.zeros(3 * y.size * 8, device="cuda")
+    x, st = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 200, tol=1e-4, state=state)
+    nu = host(state).reshape((3,) + shape)
+    d = nu - O.shrink(nu, LAM_TV / MU)
+    assert np.sqrt((d ** 2).sum(0)).max() <= (LAM_TV / MU) * (1 + 1e-5)
+    assert np.isfinite(st.objective) and st.iters >= 1
+    print(f"256^3 stop: iters {st.iters} converged {st.converged} "
+          f"primal {st.primal_rel:.3e} dual {st.dual_rel:.3e}")
