@@ -89,6 +89,8 @@ typedef struct {
 #define SR3D_FP64_REDUCE 0x1   /* residual/objective reductions and the stopping test in FP64 (else FP32) */
 #define SR3D_RESUME      0x2   /* start from problem.state (must be non-NULL) */
 #define SR3D_USE_GRAPH   0x4   /* replay captured iterations as a HIP graph */
+#define SR3D_PROFILE     0x8   /* time every kernel launch with HIP events on the caller's
+                                  stream; totals per stage via sr3d_profile_read (no graph) */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */
@@ -140,6 +142,15 @@ int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf,
  * that sr3d_irfft3d(sr3d_rfft3d(v)) = v). The inverse overwrites `spec`. */
 int sr3d_rfft3d(sr3d_dims dims, const float *in, float *spec, hipStream_t stream);
 int sr3d_irfft3d(sr3d_dims dims, float *spec, float *out, hipStream_t stream);
+
+/* Per-stage kernel timing gathered by calls made with SR3D_PROFILE (a
+ * tracing aid). Stage indices run from 0 while the call returns SR3D_OK;
+ * past the last stage it returns SR3D_ERR_INVALID_ARG. *name is a static
+ * string, *total_ms the summed HIP-event time of the stage's launches and
+ * *launches their count. Any output pointer may be NULL. */
+int sr3d_profile_read(int stage, const char **name, double *total_ms, long *launches);
+/* Clears the per-stage totals. */
+void sr3d_profile_reset(void);
 
 /* Human-readable name of a status code. */
 const char *sr3d_status_string(int status);

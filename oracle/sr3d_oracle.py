@@ -45,7 +45,15 @@ __all__ = [
     "rel_l2",
 ]
 
-WORKERS = os.cpu_count() or 1
+def _cpu_share():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+WORKERS = _cpu_share()  # scipy.fft threads: this process's CPU share, at most 16
 
 
 def _fftn(a):

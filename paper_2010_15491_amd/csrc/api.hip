@@ -13,6 +13,80 @@
 namespace sr3d {
 void release_device_tables();
 thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------
+// SR3D_PROFILE: HIP events around every launch of the calling thread.
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfState {
+  bool active = false;
+  int override_stage = -1;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> stage_of;
+  size_t used = 0;
+};
+thread_local ProfState t_prof;
+std::mutex g_prof_mu;
+double g_prof_ms[kStCount] = {0};
+long g_prof_n[kStCount] = {0};
+const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
+                                     "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "stencil_a",
+                                     "stencil_b", "reduce_test", "setup"};
+}  // namespace
+
+void prof_begin(int stage, hipStream_t st) {
+  ProfState &p = t_prof;
+  if (!p.active) return;
+  while (p.pool.size() < p.used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      p.active = false;
+      return;
+    }
+    p.pool.push_back(e);
+  }
+  if (p.stage_of.size() < p.pool.size() / 2 + 1) p.stage_of.resize(p.pool.size() / 2 + 1);
+  p.stage_of[p.used / 2] = p.override_stage >= 0 ? p.override_stage : stage;
+  (void)hipEventRecord(p.pool[p.used++], st);
+}
+
+void prof_end(hipStream_t st) {
+  ProfState &p = t_prof;
+  if (!p.active || (p.used & 1) == 0) return;
+  (void)hipEventRecord(p.pool[p.used++], st);
+}
+
+// Adds the recorded pairs to the totals; the stream must have been synchronised.
+static void prof_flush() {
+  ProfState &p = t_prof;
+  if (p.used == 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (size_t i = 0; i + 1 < p.used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.pool[i], p.pool[i + 1]) == hipSuccess) {
+      g_prof_ms[p.stage_of[i / 2]] += ms;
+      g_prof_n[p.stage_of[i / 2]] += 1;
+    }
+  }
+  p.used = 0;
+}
+
+struct ProfScope {
+  bool on;
+  ProfScope(bool enable) : on(enable) {
+    if (on) {
+      t_prof.active = true;
+      t_prof.used = 0;
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      prof_flush();
+      t_prof.active = false;
+      t_prof.override_stage = -1;
+    }
+  }
+};
 }  // namespace sr3d
 
 using namespace sr3d;
@@ -248,7 +322,10 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   SR3D_TRY(ensure_device_tables(), "twiddle tables");
   const bool fp64 = (flags & SR3D_FP64_REDUCE) != 0;
   float *nu = p->state ? p->state : L.nu;
+  ProfScope prof((flags & SR3D_PROFILE) && !(flags & SR3D_USE_GRAPH));
+  t_prof.override_stage = prof.on ? kStSetup : -1;
   SR3D_TRY(tv_setup(g, L, p, nu, flags, fp64, st), "tv setup");
+  t_prof.override_stage = -1;
   const int K = check_interval(flags);
   if (flags & SR3D_USE_GRAPH) {
     // Capture K iterations once on a private stream, replay until done.
@@ -286,6 +363,7 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
       it += n;
       SR3D_TRY(hipMemcpyAsync(hc, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
       SR3D_TRY(hipStreamSynchronize(st), "stream sync");
+      if (prof.on) prof_flush();
       if (hc->done) break;
     }
   }
@@ -439,6 +517,23 @@ const char *sr3d_status_string(int s) {
 }
 
 const char *sr3d_last_error(void) { return g_err.c_str(); }
+
+int sr3d_profile_read(int stage, const char **name, double *total_ms, long *launches) {
+  if (stage < 0 || stage >= kStCount) return SR3D_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (name) *name = kStageNames[stage];
+  if (total_ms) *total_ms = g_prof_ms[stage];
+  if (launches) *launches = g_prof_n[stage];
+  return SR3D_OK;
+}
+
+void sr3d_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < kStCount; ++i) {
+    g_prof_ms[i] = 0.0;
+    g_prof_n[i] = 0;
+  }
+}
 
 void sr3d_shutdown(void) {
   release_device_tables();

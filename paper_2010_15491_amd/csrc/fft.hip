@@ -374,8 +374,8 @@ void release_device_tables() {
 // Launchers
 // ---------------------------------------------------------------------------
 
-static hipError_t launch_r2c_m(const float *in, float2 *out, long nrows, int M, const int *done,
-                               hipStream_t st) {
+static hipError_t launch_r2c_m_(const float *in, float2 *out, long nrows, int M, const int *done,
+                                hipStream_t st) {
   if (M == 1) {
     const long n = nrows;
     hipLaunchKernelGGL(k_copy_r2c1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out,
@@ -400,8 +400,8 @@ static hipError_t launch_r2c_m(const float *in, float2 *out, long nrows, int M, 
   return hipGetLastError();
 }
 
-static hipError_t launch_c2r_m(const float2 *in, float *out, long nrows, int M, float scale,
-                               const int *done, hipStream_t st) {
+static hipError_t launch_c2r_m_(const float2 *in, float *out, long nrows, int M, float scale,
+                                const int *done, hipStream_t st) {
   if (M == 1) {
     const long n = nrows;
     hipLaunchKernelGGL(k_copy_c2r1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out,
@@ -426,8 +426,8 @@ static hipError_t launch_c2r_m(const float2 *in, float *out, long nrows, int M, 
   return hipGetLastError();
 }
 
-static hipError_t launch_strided(float2 *data, int L, long ncols, long inner, long outer_stride,
-                                 long estride, bool inv, const int *done, hipStream_t st) {
+static hipError_t launch_strided_(float2 *data, int L, long ncols, long inner, long outer_stride,
+                                  long estride, bool inv, const int *done, hipStream_t st) {
   if (L == 1) return hipSuccess;
   const float2 *tw = twiddles(L);
   if (!tw) return hipErrorInvalidValue;
@@ -453,22 +453,50 @@ static hipError_t launch_strided(float2 *data, int L, long ncols, long inner, lo
   return hipGetLastError();
 }
 
+static hipError_t launch_r2c_m(const float *in, float2 *out, long nrows, int M, const int *done,
+                               hipStream_t st) {
+  prof_begin(kStFftR2cM, st);
+  hipError_t e = launch_r2c_m_(in, out, nrows, M, done, st);
+  prof_end(st);
+  return e;
+}
+
+static hipError_t launch_c2r_m(const float2 *in, float *out, long nrows, int M, float scale,
+                               const int *done, hipStream_t st) {
+  prof_begin(kStIfftC2rM, st);
+  hipError_t e = launch_c2r_m_(in, out, nrows, M, scale, done, st);
+  prof_end(st);
+  return e;
+}
+
+static hipError_t launch_strided(float2 *data, int L, long ncols, long inner, long outer_stride,
+                                 long estride, bool inv, const int *done, hipStream_t st,
+                                 int stage) {
+  if (L == 1) return hipSuccess;
+  prof_begin(stage, st);
+  hipError_t e = launch_strided_(data, L, ncols, inner, outer_stride, estride, inv, done, st);
+  prof_end(st);
+  return e;
+}
+
 hipError_t fft3d_forward(const float *in, float2 *spec, int S, int N, int M, const int *done,
                          hipStream_t st) {
   const long Mh = M / 2 + 1;
   hipError_t e = launch_r2c_m(in, spec, (long)S * N, M, done, st);
   if (e != hipSuccess) return e;
-  e = launch_strided(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, false, done, st);
+  e = launch_strided(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, false, done, st, kStFftN);
   if (e != hipSuccess) return e;
-  return launch_strided(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, false, done, st);
+  return launch_strided(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, false, done, st,
+                        kStFftS);
 }
 
 hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                          const int *done, hipStream_t st) {
   const long Mh = M / 2 + 1;
-  hipError_t e = launch_strided(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, true, done, st);
+  hipError_t e = launch_strided(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, true, done,
+                                st, kStIfftS);
   if (e != hipSuccess) return e;
-  e = launch_strided(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, true, done, st);
+  e = launch_strided(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, true, done, st, kStIfftN);
   if (e != hipSuccess) return e;
   return launch_c2r_m(spec, out, (long)S * N, M, scale, done, st);
 }

@@ -227,7 +227,10 @@ static hipError_t launch_fold(const FoldArgs &a, hipStream_t st) {
 }
 
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st) {
-  return fp64 ? launch_fold<double>(a, st) : launch_fold<float>(a, st);
+  prof_begin(kStFold, st);
+  hipError_t e = fp64 ? launch_fold<double>(a, st) : launch_fold<float>(a, st);
+  prof_end(st);
+  return e;
 }
 
 }  // namespace sr3d

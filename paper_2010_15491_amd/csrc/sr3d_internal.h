@@ -48,6 +48,15 @@ struct FastDiv {
   }
 };
 
+// Per-stage HIP-event timing (SR3D_PROFILE). prof_begin/prof_end bracket a
+// launch on its stream when the calling thread has profiling switched on.
+enum Stage {
+  kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
+  kStStencilA, kStStencilB, kStReduce, kStSetup, kStCount
+};
+void prof_begin(int stage, hipStream_t st);
+void prof_end(hipStream_t st);
+
 bool fft_len_supported(int n);
 // Device twiddle table exp(-2 pi i k / n), k < n, for the current device.
 const float2 *twiddles(int n);

@@ -189,6 +189,7 @@ hipError_t stencil_a(const StencilArgs &a, int mode, bool fp64, hipStream_t st) 
   const int nb = stencil_blocks(a.S, a.N, a.M);
   FastDiv dm((uint32_t)a.M), dn((uint32_t)a.N);
   dim3 g(nb), b(kThreads);
+  prof_begin(kStStencilA, st);
 #define SR3D_LA(ACC, MD) hipLaunchKernelGGL((k_stencil_a<ACC, MD>), g, b, 0, st, a, dm, dn, nb)
   if (fp64) {
     if (mode == 0) SR3D_LA(double, 0);
@@ -200,13 +201,16 @@ hipError_t stencil_a(const StencilArgs &a, int mode, bool fp64, hipStream_t st) 
     else SR3D_LA(float, 2);
   }
 #undef SR3D_LA
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  prof_end(st);
+  return e;
 }
 
 hipError_t stencil_b(const StencilArgs &a, int init, bool fp64, hipStream_t st) {
   const int nb = stencil_blocks(a.S, a.N, a.M);
   FastDiv dm((uint32_t)a.M), dn((uint32_t)a.N);
   dim3 g(nb), b(kThreads);
+  prof_begin(kStStencilB, st);
 #define SR3D_LB(ACC, IN) hipLaunchKernelGGL((k_stencil_b<ACC, IN>), g, b, 0, st, a, dm, dn, nb)
   if (fp64) {
     if (init) SR3D_LB(double, 1);
@@ -216,7 +220,9 @@ hipError_t stencil_b(const StencilArgs &a, int init, bool fp64, hipStream_t st) 
     else SR3D_LB(float, 0);
   }
 #undef SR3D_LB
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  prof_end(st);
+  return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,6 +282,7 @@ __global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *pa, in
 
 hipError_t reduce_and_test(Ctrl *ctrl, const void *partA, int nbA, const void *partB, int nbB,
                            const void *partF, int nbF, bool fp64, hipStream_t st) {
+  prof_begin(kStReduce, st);
   if (fp64)
     hipLaunchKernelGGL(k_reduce_test<double>, dim3(1), dim3(1024), 0, st, ctrl,
                        (const double *)partA, nbA, (const double *)partB, nbB,
@@ -284,7 +291,9 @@ hipError_t reduce_and_test(Ctrl *ctrl, const void *partA, int nbA, const void *p
     hipLaunchKernelGGL(k_reduce_test<float>, dim3(1), dim3(1024), 0, st, ctrl,
                        (const float *)partA, nbA, (const float *)partB, nbB,
                        (const float *)partF, nbF);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  prof_end(st);
+  return e;
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,7 @@ STATUS = {0: "SR3D_OK", -1: "SR3D_ERR_INVALID_ARG", -2: "SR3D_ERR_NOT_DIVISIBLE"
 FP64_REDUCE = 0x1
 RESUME = 0x2
 USE_GRAPH = 0x4
+PROFILE = 0x8
 
 
 def CHECK_INTERVAL(k):
@@ -33,8 +34,8 @@ def CHECK_INTERVAL(k):
 OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
 
 EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
-           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_status_string",
-           "sr3d_last_error", "sr3d_shutdown"]
+           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_profile_read",
+           "sr3d_profile_reset", "sr3d_status_string", "sr3d_last_error", "sr3d_shutdown"]
 
 
 class Dims(ctypes.Structure):
@@ -93,6 +94,12 @@ def load():
         lib.sr3d_status_string.restype = ctypes.c_char_p
         lib.sr3d_last_error.argtypes = []
         lib.sr3d_last_error.restype = ctypes.c_char_p
+        lib.sr3d_profile_read.argtypes = [ci, ctypes.POINTER(ctypes.c_char_p),
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_long)]
+        lib.sr3d_profile_read.restype = ci
+        lib.sr3d_profile_reset.argtypes = []
+        lib.sr3d_profile_reset.restype = None
         lib.sr3d_shutdown.argtypes = []
         lib.sr3d_shutdown.restype = None
         _lib = lib
@@ -270,6 +277,24 @@ def irfft3d(spec, shape, stream=None):
         raise ValueError("spectrum must be contiguous")
     out = torch.empty(tuple(shape), dtype=torch.float32, device=spec.device)
     _check(load().sr3d_irfft3d(dims_of(shape), _ptr(sp), _ptr(out), _stream(stream)))
+    return out
+
+
+def profile_reset():
+    load().sr3d_profile_reset()
+
+
+def profile_read():
+    """{stage name: (total_ms, launches)} gathered by calls made with PROFILE."""
+    lib = load()
+    out = {}
+    i = 0
+    while True:
+        name, ms, n = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_long()
+        if lib.sr3d_profile_read(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(n)) != 0:
+            break
+        out[name.value.decode()] = (ms.value, n.value)
+        i += 1
     return out
 
 
