@@ -143,6 +143,21 @@ int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf,
 int sr3d_rfft3d(sr3d_dims dims, const float *in, float *spec, hipStream_t stream);
 int sr3d_irfft3d(sr3d_dims dims, float *spec, float *out, hipStream_t stream);
 
+/* FFT autotuner. Every axis kernel (R2C/C2R along m, forward/inverse along n
+ * and s) comes in tile variants of 2048, 4096 and 8192 complex elements per
+ * workgroup. sr3d_autotune times each variant for every HR and LR transform
+ * that problems p[0..count-1] need and keeps the fastest per (axis kind,
+ * length) for all later calls on this process; lengths already tuned are
+ * skipped unless `force` is non-zero. It allocates scratch device memory,
+ * synchronises `stream`, and must not run under graph capture. The choices
+ * can be written to and read from a text file (one "kind length variant" per
+ * line). Untuned lengths use the 4096-element tile. */
+int sr3d_autotune(const sr3d_problem *p, int count, int force, hipStream_t stream);
+int sr3d_tune_save(const char *path);
+/* Returns the number of entries read, or SR3D_ERR_INVALID_ARG if the file
+ * cannot be opened. */
+int sr3d_tune_load(const char *path);
+
 /* Per-stage kernel timing gathered by calls made with SR3D_PROFILE (a
  * tracing aid). Stage indices run from 0 while the call returns SR3D_OK;
  * past the last stage it returns SR3D_ERR_INVALID_ARG. *name is a static

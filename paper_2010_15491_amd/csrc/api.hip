@@ -30,8 +30,8 @@ std::mutex g_prof_mu;
 double g_prof_ms[kStCount] = {0};
 long g_prof_n[kStCount] = {0};
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
-                                     "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "stencil_a",
-                                     "stencil_b", "reduce_test", "setup"};
+                                     "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
+                                     "reduce_test", "setup"};
 }  // namespace
 
 void prof_begin(int stage, hipStream_t st) {
@@ -170,31 +170,32 @@ struct Carve {
 
 struct TvWs {
   Ctrl *ctrl;
-  void *partA, *partB, *partF;
+  void *partS, *partF;
   float *g;
   float2 *lam, *yh, *w, *w2;
-  float *nu, *theta, *ltu;
-  int nbA, nbF;
+  float *nu[2], *theta;
+  int nbS, nbF;
 };
 
+// Workspace of one TV solve. nu[0] is only used when the caller passes no
+// state buffer.
 size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   Carve c{base, 0};
-  L->nbA = stencil_blocks(g.S, g.N, g.M);
+  L->nbS = stencil_plan(g.S, g.N, g.M).blocks;
   FoldArgs fa{};
   fa.Sl = g.Sl; fa.Nl = g.Nl; fa.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
   L->nbF = fold_blocks(fa);
   L->ctrl = c.take<Ctrl>(1);
-  L->partA = c.take<double>((size_t)4 * L->nbA);
-  L->partB = c.take<double>((size_t)2 * L->nbA);
+  L->partS = c.take<double>((size_t)6 * L->nbS);
   L->partF = c.take<double>((size_t)L->nbF);
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
   L->lam = c.take<float2>(g.nspec);
   L->yh = c.take<float2>(g.nlspec);
   L->w = c.take<float2>(g.nspec);
   L->w2 = c.take<float2>(g.nspec);
-  L->nu = c.take<float>((size_t)3 * g.NH);
+  L->nu[0] = c.take<float>((size_t)3 * g.NH);
+  L->nu[1] = c.take<float>((size_t)3 * g.NH);
   L->theta = c.take<float>(g.NH);
-  L->ltu = c.take<float>(g.NH);
   return c.off + 256;
 }
 
@@ -263,27 +264,26 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
   return SR3D_OK;
 }
 
-// Enqueue setup and initial state for one TV problem.
-hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu, int flags,
-                    bool fp64, hipStream_t st) {
+// Enqueue setup and initial state (nu in nu0, Theta) for one TV problem.
+hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu0, int flags,
+                    hipStream_t st) {
   hipError_t e;
   if ((e = ctrl_init(L.ctrl, p->max_iter, p->tol, p->mu, p->lambda_tv, 1.0 / (double)g.NL, st))) return e;
   if ((e = pad_psf(p->psf, p->psf_dims.s, p->psf_dims.n, p->psf_dims.m, L.theta, g.S, g.N, g.M, st))) return e;
   if ((e = fft3d_forward(L.theta, L.lam, g.S, g.N, g.M, nullptr, st))) return e;
   if ((e = fft3d_forward(p->y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st))) return e;
   if ((e = diff_tables(L.g, g.S, g.N, g.M, st))) return e;
-  StencilArgs sa{};
-  sa.x = p->x0; sa.nu = nu; sa.theta = L.theta; sa.ltu = L.ltu;
-  sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
-  sa.partA = L.partA; sa.partB = L.partB; sa.done = nullptr;
-  if (!(flags & SR3D_RESUME)) {
-    if ((e = stencil_a(sa, p->x0 ? 1 : 2, fp64, st))) return e;
-  }
-  return stencil_b(sa, 1, fp64, st);
+  const float thr = p->lambda_tv / p->mu;
+  if (flags & SR3D_RESUME) return theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st);
+  AdmmStencilArgs sa{};
+  sa.x = p->x0; sa.nu_in = nullptr; sa.nu_out = nu0; sa.theta = L.theta;
+  sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = thr; sa.part = nullptr; sa.done = nullptr;
+  return admm_stencil(sa, false, false, st);
 }
 
-hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu, bool fp64,
-                        hipStream_t st) {
+// Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2].
+hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
+                        int k, bool fp64, hipStream_t st) {
   const int *done = &L.ctrl->done;
   hipError_t e;
   if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
@@ -294,13 +294,12 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
   fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
   if ((e = fold_solve(fa, fp64, st))) return e;
   if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
-  StencilArgs sa{};
-  sa.x = p->x; sa.nu = nu; sa.theta = L.theta; sa.ltu = L.ltu;
+  AdmmStencilArgs sa{};
+  sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
-  sa.partA = L.partA; sa.partB = L.partB; sa.done = done;
-  if ((e = stencil_a(sa, 0, fp64, st))) return e;
-  if ((e = stencil_b(sa, 0, fp64, st))) return e;
-  return reduce_and_test(L.ctrl, L.partA, L.nbA, L.partB, L.nbA, L.partF, L.nbF, fp64, st);
+  sa.part = L.partS; sa.done = done;
+  if ((e = admm_stencil(sa, true, fp64, st))) return e;
+  return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
 }
 
 int check_interval(int flags) {
@@ -321,14 +320,16 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
   SR3D_TRY(ensure_device_tables(), "twiddle tables");
   const bool fp64 = (flags & SR3D_FP64_REDUCE) != 0;
-  float *nu = p->state ? p->state : L.nu;
+  float *nu[2] = {p->state ? p->state : L.nu[0], L.nu[1]};
   ProfScope prof((flags & SR3D_PROFILE) && !(flags & SR3D_USE_GRAPH));
   t_prof.override_stage = prof.on ? kStSetup : -1;
-  SR3D_TRY(tv_setup(g, L, p, nu, flags, fp64, st), "tv setup");
+  SR3D_TRY(tv_setup(g, L, p, nu[0], flags, st), "tv setup");
   t_prof.override_stage = -1;
-  const int K = check_interval(flags);
+  int K = check_interval(flags);
   if (flags & SR3D_USE_GRAPH) {
-    // Capture K iterations once on a private stream, replay until done.
+    // Capture K iterations (K even, so the two state buffers alternate the
+    // same way in every replay) on a private stream; replay until done.
+    K += K & 1;
     hipStream_t cs;
     SR3D_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream create");
     hipEvent_t ev;
@@ -336,7 +337,7 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int i = 0; e == hipSuccess && i < K; ++i) e = tv_iteration(g, L, p, nu, fp64, cs);
+    for (int i = 1; e == hipSuccess && i <= K; ++i) e = tv_iteration(g, L, p, nu, i, fp64, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -359,13 +360,19 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   } else {
     for (int it = 0; it < p->max_iter;) {
       const int n = (p->max_iter - it) < K ? (p->max_iter - it) : K;
-      for (int i = 0; i < n; ++i) SR3D_TRY(tv_iteration(g, L, p, nu, fp64, st), "tv iteration");
+      for (int i = 1; i <= n; ++i) SR3D_TRY(tv_iteration(g, L, p, nu, it + i, fp64, st), "tv iteration");
       it += n;
       SR3D_TRY(hipMemcpyAsync(hc, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
       SR3D_TRY(hipStreamSynchronize(st), "stream sync");
       if (prof.on) prof_flush();
       if (hc->done) break;
     }
+  }
+  // The latest state is in nu[iter % 2]; hand it back in the caller's buffer.
+  if (p->state && (hc->iter & 1)) {
+    SR3D_TRY(hipMemcpyAsync(p->state, nu[1], sizeof(float) * 3 * (size_t)g.NH,
+                            hipMemcpyDeviceToDevice, st), "state copy");
+    SR3D_TRY(hipStreamSynchronize(st), "stream sync");
   }
   if (stats) {
     stats->iters = hc->iter;
@@ -517,6 +524,33 @@ const char *sr3d_status_string(int s) {
 }
 
 const char *sr3d_last_error(void) { return g_err.c_str(); }
+
+int sr3d_autotune(const sr3d_problem *p, int count, int force, hipStream_t st) {
+  if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
+  Geometry g;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &g);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < count; ++i) {
+    check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &g);
+    SR3D_TRY(fft_autotune(g.S, g.N, g.M, force != 0, st), "autotune HR");
+    SR3D_TRY(fft_autotune(g.Sl, g.Nl, g.Ml, force != 0, st), "autotune LR");
+  }
+  return SR3D_OK;
+}
+
+int sr3d_tune_save(const char *path) {
+  if (!path || fft_tune_save(path) != 0) return fail(SR3D_ERR_INVALID_ARG, "cannot write tune file");
+  return SR3D_OK;
+}
+
+int sr3d_tune_load(const char *path) {
+  if (!path) return fail(SR3D_ERR_INVALID_ARG, "NULL path");
+  const int n = fft_tune_load(path);
+  if (n < 0) return fail(SR3D_ERR_INVALID_ARG, "cannot read tune file");
+  return n;
+}
 
 int sr3d_profile_read(int stage, const char **name, double *total_ms, long *launches) {
   if (stage < 0 || stage >= kStCount) return SR3D_ERR_INVALID_ARG;

@@ -10,8 +10,6 @@ namespace sr3d {
 
 constexpr int kThreads = 256;      // threads per workgroup for every kernel here
 constexpr int kMaxLen = 1024;      // largest FFT length supported
-constexpr int kStencilVpt = 8;     // voxels per thread in the stencil kernels
-constexpr int kStencilVox = kThreads * kStencilVpt;
 
 // Device-side solver control block: the stop flag every predicated kernel
 // reads, the iteration counter and the latest stopping-test values.
@@ -52,12 +50,33 @@ struct FastDiv {
 // launch on its stream when the calling thread has profiling switched on.
 enum Stage {
   kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
-  kStStencilA, kStStencilB, kStReduce, kStSetup, kStCount
+  kStStencil, kStReduce, kStSetup, kStCount
 };
 void prof_begin(int stage, hipStream_t st);
 void prof_end(hipStream_t st);
 
+#define SR3D_FFT_LENGTHS(X) \
+  X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
+  X(384) X(512) X(768) X(1024)
+
 bool fft_len_supported(int n);
+
+// Axis kernels and their tile variants (fft_m.hip, fft_strided.hip).
+enum FftKind { kFftR2cM, kFftC2rM, kFftFwdN, kFftInvN, kFftFwdS, kFftInvS, kFftKinds };
+hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
+                          hipStream_t st);
+hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
+                          const int *done, hipStream_t st);
+hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
+                            long estride, bool inv, int v, const int *done, hipStream_t st);
+int fft_variant(int kind, int len);
+void fft_set_variant(int kind, int len, int v);
+// Times every tile variant of every axis kernel a volume S x N x M uses and
+// keeps the fastest (skips lengths already tuned unless force). Allocates
+// scratch with hipMalloc and synchronises the stream.
+hipError_t fft_autotune(int S, int N, int M, bool force, hipStream_t st);
+int fft_tune_save(const char *path);
+int fft_tune_load(const char *path);
 // Device twiddle table exp(-2 pi i k / n), k < n, for the current device.
 const float2 *twiddles(int n);
 hipError_t ensure_device_tables();
@@ -92,28 +111,29 @@ struct FoldArgs {
 int fold_blocks(const FoldArgs &a);
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
 
-// Difference / shrink / dual kernels (Algorithm 1 steps 5b, 5c and the Theta
-// of 5a). State nu = L x + d_prev holds (u, d): u = shrink(nu), d = nu - u.
-struct StencilArgs {
-  const float *x;
-  float *nu;          // [3][N_h]
-  float *theta;       // N_h: L^T (u - d)
-  float *ltu;         // N_h: L^T u of the previous iteration (dual residual)
+// Fused difference / shrink / dual / Theta pass (Algorithm 1 steps 5b, 5c and
+// the Theta of the next 5a). State nu = L x + d_prev holds (u, d):
+// u = shrink(nu), d = nu - u.
+struct AdmmStencilArgs {
+  const float *x;      // HR volume, or null for x = 0
+  const float *nu_in;  // [3][N_h] state before the step, or null (initialisation: d = 0)
+  float *nu_out;       // [3][N_h] state after the step (must not alias nu_in)
+  float *theta;        // N_h: L^T (u' - d')
   int S, N, M;
-  float thr;          // lambda / mu
-  void *partA;        // [4][blocks] : |Lx-u'|^2, |Lx|^2, |u'|^2, sum |(Lx)_j|
-  void *partB;        // [2][blocks] : |L^T(u'-u)|^2, |L^T d'|^2
+  float thr;           // lambda / mu
+  void *part;          // [6][blocks]: |Lx-u'|^2, |Lx|^2, |u'|^2, sum|(Lx)_j|, |L^T(u'-u)|^2, |L^T d'|^2
   const int *done;
 };
-int stencil_blocks(int S, int N, int M);
-// mode 0: iteration (nu <- L x + d(nu)); mode 1: init from x (nu <- L x);
-// mode 2: init with x = 0 (nu <- 0).
-hipError_t stencil_a(const StencilArgs &a, int mode, bool fp64, hipStream_t st);
-// init != 0: first pass, no residual sums (ltu written only).
-hipError_t stencil_b(const StencilArgs &a, int init, bool fp64, hipStream_t st);
+struct StencilPlan {
+  int tiles_m, tiles_n, chunks, L, blocks;
+};
+StencilPlan stencil_plan(int S, int N, int M);
+hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st);
+hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,
+                         hipStream_t st);
 // Final reduction of the partial sums and the stopping test.
-hipError_t reduce_and_test(Ctrl *ctrl, const void *partA, int nbA, const void *partB, int nbB,
-                           const void *partF, int nbF, bool fp64, hipStream_t st);
+hipError_t reduce_and_test(Ctrl *ctrl, const void *partS, int nbS, const void *partF, int nbF,
+                           bool fp64, hipStream_t st);
 
 // Setup kernels.
 hipError_t pad_psf(const float *psf, int Ks, int Kn, int Km, float *out, int S, int N, int M,

@@ -1,20 +1,24 @@
-// Difference / isotropic shrink / dual update (Algorithm 1 steps 5b, 5c) and
-// the Theta = L^T (u - d) of the next step 5a, plus the residual reductions of
-// the stopping rule.
+// Difference / isotropic shrink / dual update (Algorithm 1 steps 5b, 5c), the
+// Theta = L^T (u - d) of the next step 5a, and the residual reductions of the
+// stopping rule, fused into one pass over the volume.
 //
 // The ADMM state (u, d) is carried as nu = L x + d_prev (3 planes): step 5b
 // gives u = shrink(nu) and step 5c gives d = d_prev + (L x - u) = nu - u, so
-// (u, d) are functions of nu alone. This halves the state traffic.
+// (u, d) are functions of nu alone. One iteration reads x and nu_old and
+// writes nu_new and Theta (32 bytes per voxel); nu is double-buffered because
+// neighbouring workgroups read nu_old across tile borders.
 //
-// stencil_a (per voxel i): L x with periodic forward differences,
-//   nu' = L x + d(nu), u' = shrink(nu'), accumulates |Lx-u'|^2 (= |d'-d|^2),
-//   |Lx|^2, |u'|^2 and the TV term |(Lx)_i|.
-// stencil_b (per voxel i): u', d' at i and at i - e_a (a = m, n, s),
-//   Theta = L^T u' - L^T d', accumulates |L^T u' - L^T u|^2 and |L^T d'|^2,
-//   and stores L^T u' for the next dual residual.
-// Each workgroup covers kStencilVox consecutive voxels, taken in an XCD-aware
-// order so the planes a workgroup touches stay in one XCD's L2.
+// A workgroup owns a 16 (n) x 32 (m) column tile and marches along s through
+// a chunk of planes. Per plane it stages x with a one-voxel ring in LDS
+// (forward differences), recomputes nu_new, u, d on the tile plus its lower
+// n and m faces (the backward neighbours L^T needs), and keeps the s-component
+// of the previous plane in registers, so the s halo costs nothing.
 #include "sr3d_internal.h"
+
+// No FMA contraction in this file: the resume path (k_theta_from_nu) must
+// reproduce the fused kernel's Theta bit for bit, which requires both to round
+// every product and sum the same way.
+#pragma clang fp contract(off)
 
 namespace sr3d {
 
@@ -27,6 +31,7 @@ __device__ __forceinline__ void block_reduce_n(T *v, int n, T *sh /* [n][4] */) 
     v[q] = s;
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0)
     for (int q = 0; q < n; ++q) sh[q * 4 + wid] = v[q];
   __syncthreads();
@@ -35,7 +40,7 @@ __device__ __forceinline__ void block_reduce_n(T *v, int n, T *sh /* [n][4] */) 
 }
 
 // Workgroup b of nb is dispatched to XCD b % 8; give every XCD a contiguous
-// range of tiles.
+// range of tiles so neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb >> 3, r = nb & 7;
   const int x = b & 7, l = b >> 3;
@@ -55,205 +60,355 @@ __device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr,
   u2 = a2 * s;
 }
 
-template <typename Acc, int MODE>
-__global__ __launch_bounds__(kThreads) void k_stencil_a(StencilArgs a, FastDiv divM, FastDiv divN,
-                                                        int nb) {
-  if (a.done && *a.done) return;
-  __shared__ Acc sh[4 * 4];
-  const long NT = (long)a.S * a.N * a.M;
-  const long plane = (long)a.N * a.M;
-  const int tile = xcd_tile(blockIdx.x, nb);
-  Acc acc[4] = {0, 0, 0, 0};
-  for (int k = 0; k < kStencilVpt; ++k) {
-    const long v = (long)tile * kStencilVox + k * kThreads + threadIdx.x;
-    if (v >= NT) break;
-    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-    if (MODE != 2) {
-      const uint32_t r1 = divM.div((uint32_t)v);
-      const int im = (int)(v - (long)r1 * a.M);
-      const uint32_t is = divN.div(r1);
-      const int in = (int)(r1 - is * (uint32_t)a.N);
-      const long om = (im + 1 == a.M) ? -(long)(a.M - 1) : 1;
-      const long on = (in + 1 == a.N) ? -(long)(a.N - 1) * a.M : (long)a.M;
-      const long os = ((int)is + 1 == a.S) ? -(long)(a.S - 1) * plane : plane;
-      const float xi = a.x[v];
-      const float l0 = a.x[v + om] - xi, l1 = a.x[v + on] - xi, l2 = a.x[v + os] - xi;
-      float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-      if (MODE == 0) {
-        const float p0 = a.nu[v], p1 = a.nu[v + NT], p2 = a.nu[v + 2 * NT];
-        float u0, u1, u2;
-        shrink3(p0, p1, p2, a.thr, u0, u1, u2);
-        d0 = p0 - u0;
-        d1 = p1 - u1;
-        d2 = p2 - u2;
-      }
-      n0 = l0 + d0;
-      n1 = l1 + d1;
-      n2 = l2 + d2;
-      if (MODE == 0) {
-        float u0, u1, u2;
-        shrink3(n0, n1, n2, a.thr, u0, u1, u2);
-        const float r0 = l0 - u0, r1_ = l1 - u1, r2 = l2 - u2;
-        const Acc lx2 = (Acc)l0 * l0 + (Acc)l1 * l1 + (Acc)l2 * l2;
-        acc[0] += (Acc)r0 * r0 + (Acc)r1_ * r1_ + (Acc)r2 * r2;
-        acc[1] += lx2;
-        acc[2] += (Acc)u0 * u0 + (Acc)u1 * u1 + (Acc)u2 * u2;
-        acc[3] += sqrt(lx2);
-      }
-    }
-    a.nu[v] = n0;
-    a.nu[v + NT] = n1;
-    a.nu[v + 2 * NT] = n2;
-  }
-  if (MODE == 0) {
-    block_reduce_n<Acc>(acc, 4, sh);
-    if (threadIdx.x == 0) {
-      Acc *p = reinterpret_cast<Acc *>(a.partA);
-      for (int q = 0; q < 4; ++q) p[(long)q * nb + blockIdx.x] = acc[q];
-    }
+constexpr int FT_M = 32, FT_N = 16, FT_COLS = FT_M * FT_N;  // tile columns (2 per thread)
+constexpr int XR_M = FT_M + 2, XR_N = FT_N + 2, XR = XR_M * XR_N;  // x plane with ring
+constexpr int FF_M = FT_M + 1, FF_N = FT_N + 1, FF = FF_M * FF_N;  // tile + lower faces
+constexpr int NFACE = FF - FT_COLS;
+constexpr int XR_PT = (XR + kThreads - 1) / kThreads;
+
+// Quantities of one point after the update: w = u' - d', d', du = u' - u.
+struct PointQ {
+  float w[3], d[3], du[3];
+  float l[3], u[3];   // L x and u' (for the primal residual sums)
+  float nn[3];        // nu_new
+};
+
+__device__ __forceinline__ void point_update(const float *xc, const float *xn, int ri, float o0,
+                                             float o1, float o2, float thr, PointQ &q) {
+  const float xi = xc[ri];
+  q.l[0] = xc[ri + 1] - xi;
+  q.l[1] = xc[ri + XR_M] - xi;
+  q.l[2] = xn[ri] - xi;
+  float uo0, uo1, uo2;
+  shrink3(o0, o1, o2, thr, uo0, uo1, uo2);
+  q.nn[0] = q.l[0] + (o0 - uo0);
+  q.nn[1] = q.l[1] + (o1 - uo1);
+  q.nn[2] = q.l[2] + (o2 - uo2);
+  shrink3(q.nn[0], q.nn[1], q.nn[2], thr, q.u[0], q.u[1], q.u[2]);
+  const float uo[3] = {uo0, uo1, uo2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q.d[c] = q.nn[c] - q.u[c];
+    q.w[c] = q.u[c] - q.d[c];
+    q.du[c] = q.u[c] - uo[c];
   }
 }
 
-template <typename Acc, int INIT>
-__global__ __launch_bounds__(kThreads) void k_stencil_b(StencilArgs a, FastDiv divM, FastDiv divN,
-                                                        int nb) {
+template <typename Acc, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, StencilPlan pl) {
   if (a.done && *a.done) return;
-  __shared__ Acc sh[2 * 4];
-  const long NT = (long)a.S * a.N * a.M;
-  const long plane = (long)a.N * a.M;
-  const int tile = xcd_tile(blockIdx.x, nb);
-  Acc acc[2] = {0, 0};
-  for (int k = 0; k < kStencilVpt; ++k) {
-    const long v = (long)tile * kStencilVox + k * kThreads + threadIdx.x;
-    if (v >= NT) break;
-    const uint32_t r1 = divM.div((uint32_t)v);
-    const int im = (int)(v - (long)r1 * a.M);
-    const uint32_t is = divN.div(r1);
-    const int in = (int)(r1 - is * (uint32_t)a.N);
-    const long om = (im == 0) ? (long)(a.M - 1) : -1;
-    const long on = (in == 0) ? (long)(a.N - 1) * a.M : -(long)a.M;
-    const long os = (is == 0) ? (long)(a.S - 1) * plane : -plane;
-    float u0, u1, u2;
-    const float p0 = a.nu[v], p1 = a.nu[v + NT], p2 = a.nu[v + 2 * NT];
-    shrink3(p0, p1, p2, a.thr, u0, u1, u2);
-    float ltu = -(u0 + u1 + u2);
-    float ltd = -((p0 - u0) + (p1 - u1) + (p2 - u2));
-    {
-      const long w = v + om;
-      float q0, q1, q2;
-      const float s0 = a.nu[w], s1 = a.nu[w + NT], s2 = a.nu[w + 2 * NT];
-      shrink3(s0, s1, s2, a.thr, q0, q1, q2);
-      ltu += q0;
-      ltd += s0 - q0;
-    }
-    {
-      const long w = v + on;
-      float q0, q1, q2;
-      const float s0 = a.nu[w], s1 = a.nu[w + NT], s2 = a.nu[w + 2 * NT];
-      shrink3(s0, s1, s2, a.thr, q0, q1, q2);
-      ltu += q1;
-      ltd += s1 - q1;
-    }
-    {
-      const long w = v + os;
-      float q0, q1, q2;
-      const float s0 = a.nu[w], s1 = a.nu[w + NT], s2 = a.nu[w + 2 * NT];
-      shrink3(s0, s1, s2, a.thr, q0, q1, q2);
-      ltu += q2;
-      ltd += s2 - q2;
-    }
-    if (!INIT) {
-      const float old = a.ltu[v];
-      const float du = ltu - old;
-      acc[0] += (Acc)du * du;
-      acc[1] += (Acc)ltd * ltd;
-    }
-    a.ltu[v] = ltu;
-    a.theta[v] = ltu - ltd;
-  }
-  if (!INIT) {
-    block_reduce_n<Acc>(acc, 2, sh);
-    if (threadIdx.x == 0) {
-      Acc *p = reinterpret_cast<Acc *>(a.partB);
-      for (int q = 0; q < 2; ++q) p[(long)q * nb + blockIdx.x] = acc[q];
-    }
-  }
-}
+  __shared__ float xs[3][XR];
+  __shared__ float fw[2][FF], fd[2][FF], fu[2][FF];  // m and n components at tile + faces
+  __shared__ Acc sh[6 * 4];
 
-int stencil_blocks(int S, int N, int M) {
+  const int S = a.S, N = a.N, M = a.M;
   const long NT = (long)S * N * M;
-  return (int)((NT + kStencilVox - 1) / kStencilVox);
+  const long plane = (long)N * M;
+  const int b = xcd_tile(blockIdx.x, pl.blocks);
+  const int tm = b % pl.tiles_m;
+  const int tn = (b / pl.tiles_m) % pl.tiles_n;
+  const int ch = b / (pl.tiles_m * pl.tiles_n);
+  const int m0 = tm * FT_M, n0 = tn * FT_N;
+  const int s0 = ch * pl.L;
+  const int s1 = min(s0 + pl.L, S);
+  const int tid = threadIdx.x;
+
+  // Ring load items: global 2D offsets (fixed for every plane).
+  long roff[XR_PT];
+  int ridx[XR_PT];
+#pragma unroll
+  for (int k = 0; k < XR_PT; ++k) {
+    const int r = tid + k * kThreads;
+    ridx[k] = r;
+    if (r < XR) {
+      const int rn = r / XR_M, rm = r % XR_M;
+      const int gn = ((n0 + rn - 1) % N + N) % N;
+      const int gm = ((m0 + rm - 1) % M + M) % M;
+      roff[k] = (long)gn * M + gm;
+    } else {
+      roff[k] = 0;
+    }
+  }
+  // Own tile points (2) and an optional face point.
+  int pl_ln[2], pl_lm[2];
+  long poff[2];
+  bool pval[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int c = tid + k * kThreads;
+    pl_ln[k] = c / FT_M;
+    pl_lm[k] = c % FT_M;
+    const int gn = n0 + pl_ln[k], gm = m0 + pl_lm[k];
+    pval[k] = gn < N && gm < M;
+    poff[k] = (long)(gn % N) * M + (gm % M);
+  }
+  const bool has_face = tid < NFACE;
+  int f_ln = 0, f_lm = 0;
+  long foff = 0;
+  if (has_face) {
+    if (tid < FF_M) {
+      f_ln = -1;
+      f_lm = tid - 1;
+    } else {
+      f_ln = tid - FF_M;
+      f_lm = -1;
+    }
+    const int gn = ((n0 + f_ln) % N + N) % N, gm = ((m0 + f_lm) % M + M) % M;
+    foff = (long)gn * M + gm;
+  }
+
+  // Global loads are issued one plane ahead (x ring into registers, then LDS;
+  // nu_old of the next plane into registers) so their latency overlaps the
+  // arithmetic of the current plane.
+  auto ring_fetch = [&](int sp, float *xr) {
+    const int sg = ((sp % S) + S) % S;
+    const long base = (long)sg * plane;
+#pragma unroll
+    for (int k = 0; k < XR_PT; ++k)
+      xr[k] = (a.x && ridx[k] < XR) ? a.x[base + roff[k]] : 0.f;
+  };
+  auto ring_store = [&](int buf, const float *xr) {
+#pragma unroll
+    for (int k = 0; k < XR_PT; ++k)
+      if (ridx[k] < XR) xs[buf][ridx[k]] = xr[k];
+  };
+  // nu_old at the 2 tile points and the face point of plane sp
+  auto nu_fetch = [&](int sp, float (*o)[3]) {
+    const long sb = (long)(((sp % S) + S) % S) * plane;
+    const long offs[3] = {sb + poff[0], sb + poff[1], sb + foff};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (a.nu_in && (k < 2 || has_face)) {
+        o[k][0] = a.nu_in[offs[k]];
+        o[k][1] = a.nu_in[offs[k] + NT];
+        o[k][2] = a.nu_in[offs[k] + 2 * NT];
+      } else {
+        o[k][0] = o[k][1] = o[k][2] = 0.f;
+      }
+    }
+  };
+
+  Acc acc[6] = {0, 0, 0, 0, 0, 0};
+  float pw[2], pd[2], pu[2];  // s-components at the previous plane
+  float xr[XR_PT];
+  float nuc[3][3], nun[3][3];
+
+  // Prologue: plane s0 - 1 (its s-components feed L^T at plane s0).
+  {
+    float xa[XR_PT], nup[3][3];
+    ring_fetch(s0 - 1, xa);
+    ring_fetch(s0, xr);
+    nu_fetch(s0 - 1, nup);
+    ring_store(0, xa);
+    ring_store(1, xr);
+    ring_fetch(s0 + 1, xr);
+    nu_fetch(s0, nuc);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      PointQ q;
+      point_update(xs[0], xs[1], (pl_ln[k] + 1) * XR_M + pl_lm[k] + 1, nup[k][0], nup[k][1],
+                   nup[k][2], a.thr, q);
+      pw[k] = q.w[2];
+      pd[k] = q.d[2];
+      pu[k] = q.du[2];
+    }
+  }
+
+  for (int sp = s0; sp < s1; ++sp) {
+    const int bc = (sp - s0 + 1) % 3, bn = (sp - s0 + 2) % 3;
+    ring_store(bn, xr);  // plane sp + 1
+    if (sp + 1 < s1) {
+      ring_fetch(sp + 2, xr);
+      nu_fetch(sp + 1, nun);
+    }
+    __syncthreads();
+    const long sb = (long)sp * plane;
+    float sw[2], sd[2], su[2], cw[2], cd[2], cu[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      PointQ q;
+      const int ri = (pl_ln[k] + 1) * XR_M + pl_lm[k] + 1;
+      point_update(xs[bc], xs[bn], ri, nuc[k][0], nuc[k][1], nuc[k][2], a.thr, q);
+      const int fi = (pl_ln[k] + 1) * FF_M + pl_lm[k] + 1;
+      fw[0][fi] = q.w[0];
+      fw[1][fi] = q.w[1];
+      fd[0][fi] = q.d[0];
+      fd[1][fi] = q.d[1];
+      fu[0][fi] = q.du[0];
+      fu[1][fi] = q.du[1];
+      sw[k] = q.w[0] + q.w[1] + q.w[2];
+      sd[k] = q.d[0] + q.d[1] + q.d[2];
+      su[k] = q.du[0] + q.du[1] + q.du[2];
+      cw[k] = q.w[2];
+      cd[k] = q.d[2];
+      cu[k] = q.du[2];
+      if (pval[k]) {
+        const long v = sb + poff[k];
+        a.nu_out[v] = q.nn[0];
+        a.nu_out[v + NT] = q.nn[1];
+        a.nu_out[v + 2 * NT] = q.nn[2];
+        if (STATS) {
+          const Acc l2 = (Acc)q.l[0] * q.l[0] + (Acc)q.l[1] * q.l[1] + (Acc)q.l[2] * q.l[2];
+          const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
+          acc[0] += (Acc)r0 * r0 + (Acc)r1 * r1 + (Acc)r2 * r2;
+          acc[1] += l2;
+          acc[2] += (Acc)q.u[0] * q.u[0] + (Acc)q.u[1] * q.u[1] + (Acc)q.u[2] * q.u[2];
+          acc[3] += sqrt(l2);
+        }
+      }
+    }
+    if (has_face) {
+      PointQ q;
+      point_update(xs[bc], xs[bn], (f_ln + 1) * XR_M + f_lm + 1, nuc[2][0], nuc[2][1], nuc[2][2],
+                   a.thr, q);
+      const int fi = (f_ln + 1) * FF_M + f_lm + 1;
+      fw[0][fi] = q.w[0];
+      fw[1][fi] = q.w[1];
+      fd[0][fi] = q.d[0];
+      fd[1][fi] = q.d[1];
+      fu[0][fi] = q.du[0];
+      fu[1][fi] = q.du[1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int fi = (pl_ln[k] + 1) * FF_M + pl_lm[k] + 1;
+      // (L^T z)[i] = sum_a z_a[i - e_a] - sum_a z_a[i]
+      const float ltw = fw[0][fi - 1] + fw[1][fi - FF_M] + pw[k] - sw[k];
+      const float ltd = fd[0][fi - 1] + fd[1][fi - FF_M] + pd[k] - sd[k];
+      const float ltu = fu[0][fi - 1] + fu[1][fi - FF_M] + pu[k] - su[k];
+      if (pval[k]) {
+        a.theta[sb + poff[k]] = ltw;
+        if (STATS) {
+          acc[4] += (Acc)ltu * ltu;
+          acc[5] += (Acc)ltd * ltd;
+        }
+      }
+      pw[k] = cw[k];
+      pd[k] = cd[k];
+      pu[k] = cu[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nuc[k][c] = nun[k][c];
+  }
+  if (STATS) {
+    block_reduce_n<Acc>(acc, 6, sh);
+    if (tid == 0) {
+      Acc *p = reinterpret_cast<Acc *>(a.part);
+      for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + blockIdx.x] = acc[q];
+    }
+  }
 }
 
-hipError_t stencil_a(const StencilArgs &a, int mode, bool fp64, hipStream_t st) {
-  const int nb = stencil_blocks(a.S, a.N, a.M);
-  FastDiv dm((uint32_t)a.M), dn((uint32_t)a.N);
-  dim3 g(nb), b(kThreads);
-  prof_begin(kStStencilA, st);
-#define SR3D_LA(ACC, MD) hipLaunchKernelGGL((k_stencil_a<ACC, MD>), g, b, 0, st, a, dm, dn, nb)
-  if (fp64) {
-    if (mode == 0) SR3D_LA(double, 0);
-    else if (mode == 1) SR3D_LA(double, 1);
-    else SR3D_LA(double, 2);
+StencilPlan stencil_plan(int S, int N, int M) {
+  StencilPlan p;
+  p.tiles_m = (M + FT_M - 1) / FT_M;
+  p.tiles_n = (N + FT_N - 1) / FT_N;
+  const long cols = (long)p.tiles_m * p.tiles_n;
+  long L = (S * cols + 2047) / 2048;
+  if (L < 2) L = 2;
+  if (L > 32) L = 32;
+  if (L > S) L = S;
+  p.L = (int)L;
+  p.chunks = (S + p.L - 1) / p.L;
+  p.blocks = (int)(cols * p.chunks);
+  return p;
+}
+
+hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st) {
+  const StencilPlan pl = stencil_plan(a.S, a.N, a.M);
+  dim3 g(pl.blocks), b(kThreads);
+  prof_begin(kStStencil, st);
+  if (stats) {
+    if (fp64) hipLaunchKernelGGL((k_admm_stencil<double, true>), g, b, 0, st, a, pl);
+    else hipLaunchKernelGGL((k_admm_stencil<float, true>), g, b, 0, st, a, pl);
   } else {
-    if (mode == 0) SR3D_LA(float, 0);
-    else if (mode == 1) SR3D_LA(float, 1);
-    else SR3D_LA(float, 2);
+    hipLaunchKernelGGL((k_admm_stencil<float, false>), g, b, 0, st, a, pl);
   }
-#undef SR3D_LA
   hipError_t e = hipGetLastError();
   prof_end(st);
   return e;
 }
 
-hipError_t stencil_b(const StencilArgs &a, int init, bool fp64, hipStream_t st) {
-  const int nb = stencil_blocks(a.S, a.N, a.M);
-  FastDiv dm((uint32_t)a.M), dn((uint32_t)a.N);
-  dim3 g(nb), b(kThreads);
-  prof_begin(kStStencilB, st);
-#define SR3D_LB(ACC, IN) hipLaunchKernelGGL((k_stencil_b<ACC, IN>), g, b, 0, st, a, dm, dn, nb)
-  if (fp64) {
-    if (init) SR3D_LB(double, 1);
-    else SR3D_LB(double, 0);
-  } else {
-    if (init) SR3D_LB(float, 1);
-    else SR3D_LB(float, 0);
+// Theta = L^T (u - d) of a given state nu (resuming from a checkpoint).
+__global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restrict__ nu,
+                                                            float *__restrict__ theta, int S, int N,
+                                                            int M, float thr) {
+  const long NT = (long)S * N * M;
+  const long v = (long)blockIdx.x * kThreads + threadIdx.x;
+  if (v >= NT) return;
+  const int im = (int)(v % M);
+  const long r = v / M;
+  const int in = (int)(r % N), is = (int)(r / N);
+  const long plane = (long)N * M;
+  const long nb[3] = {v + ((im == 0) ? (long)(M - 1) : -1L),
+                      v + ((in == 0) ? (long)(N - 1) * M : -(long)M),
+                      v + ((is == 0) ? (long)(S - 1) * plane : -plane)};
+  // Same operation order as k_admm_stencil, so a resumed solve continues the
+  // iteration bit for bit.
+  float u[3], w[3], nb_w[3];
+  const float p[3] = {nu[v], nu[v + NT], nu[v + 2 * NT]};
+  shrink3(p[0], p[1], p[2], thr, u[0], u[1], u[2]);
+  for (int c = 0; c < 3; ++c) {
+    const float d = p[c] - u[c];
+    w[c] = u[c] - d;
   }
-#undef SR3D_LB
-  hipError_t e = hipGetLastError();
-  prof_end(st);
-  return e;
+  const float sw = w[0] + w[1] + w[2];
+  for (int c = 0; c < 3; ++c) {
+    float q[3];
+    const float s[3] = {nu[nb[c]], nu[nb[c] + NT], nu[nb[c] + 2 * NT]};
+    shrink3(s[0], s[1], s[2], thr, q[0], q[1], q[2]);
+    const float d = s[c] - q[c];
+    nb_w[c] = q[c] - d;
+  }
+  const float t = nb_w[0] + nb_w[1] + nb_w[2] - sw;
+  theta[v] = t;
+}
+
+hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,
+                         hipStream_t st) {
+  const long NT = (long)S * N * M;
+  hipLaunchKernelGGL(k_theta_from_nu, dim3((unsigned)((NT + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, nu, theta, S, N, M, thr);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Final reduction and stopping rule (one workgroup).
 // ---------------------------------------------------------------------------
 
+// Sums of the 6 stencil partial arrays and the fold partials, all loads of a
+// thread issued before any shuffle.
 template <typename Acc>
-__device__ Acc sum_range(const Acc *p, int n, Acc *sh) {
-  Acc s = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = s;
-  __syncthreads();
-  Acc r = 0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-  return r;
-}
-
-template <typename Acc>
-__global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *pa, int nba, const Acc *pb,
-                                                      int nbb, const Acc *pf, int nbf) {
+__global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *ps, int nbs,
+                                                      const Acc *pf, int nbf) {
   if (c->done) return;
-  __shared__ Acc sh[16];
-  Acc q[7];
-  for (int k = 0; k < 4; ++k) q[k] = sum_range<Acc>(pa + (long)k * nba, nba, sh);
-  for (int k = 0; k < 2; ++k) q[4 + k] = sum_range<Acc>(pb + (long)k * nbb, nbb, sh);
-  q[6] = pf ? sum_range<Acc>(pf, nbf, sh) : (Acc)0;
+  __shared__ Acc sh[7][16];
+  Acc q[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nbs; i += 1024) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q[k] += ps[(long)k * nbs + i];
+  }
+  if (pf)
+    for (int i = threadIdx.x; i < nbf; i += 1024) q[6] += pf[i];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q[k] += __shfl_xor(q[k], off);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 7; ++k) sh[k][wid] = q[k];
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  for (int k = 0; k < 7; ++k) {
+    Acc t = 0;
+    for (int w = 0; w < 16; ++w) t += sh[k][w];
+    q[k] = t;
+  }
   bool finite = true;
   for (int k = 0; k < 7; ++k) finite = finite && isfinite(q[k]);
   const Acc mu = (Acc)c->mu, tol = (Acc)c->tol;
@@ -280,17 +435,15 @@ __global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *pa, in
   if (c->iter >= c->max_iter) c->done = 1;
 }
 
-hipError_t reduce_and_test(Ctrl *ctrl, const void *partA, int nbA, const void *partB, int nbB,
-                           const void *partF, int nbF, bool fp64, hipStream_t st) {
+hipError_t reduce_and_test(Ctrl *ctrl, const void *partS, int nbS, const void *partF, int nbF,
+                           bool fp64, hipStream_t st) {
   prof_begin(kStReduce, st);
   if (fp64)
     hipLaunchKernelGGL(k_reduce_test<double>, dim3(1), dim3(1024), 0, st, ctrl,
-                       (const double *)partA, nbA, (const double *)partB, nbB,
-                       (const double *)partF, nbF);
+                       (const double *)partS, nbS, (const double *)partF, nbF);
   else
     hipLaunchKernelGGL(k_reduce_test<float>, dim3(1), dim3(1024), 0, st, ctrl,
-                       (const float *)partA, nbA, (const float *)partB, nbB,
-                       (const float *)partF, nbF);
+                       (const float *)partS, nbS, (const float *)partF, nbF);
   hipError_t e = hipGetLastError();
   prof_end(st);
   return e;

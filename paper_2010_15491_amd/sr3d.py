@@ -34,7 +34,8 @@ def CHECK_INTERVAL(k):
 OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
 
 EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
-           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_profile_read",
+           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_autotune",
+           "sr3d_tune_save", "sr3d_tune_load", "sr3d_profile_read",
            "sr3d_profile_reset", "sr3d_status_string", "sr3d_last_error", "sr3d_shutdown"]
 
 
@@ -94,6 +95,12 @@ def load():
         lib.sr3d_status_string.restype = ctypes.c_char_p
         lib.sr3d_last_error.argtypes = []
         lib.sr3d_last_error.restype = ctypes.c_char_p
+        lib.sr3d_autotune.argtypes = [ctypes.POINTER(Problem), ci, ci, vp]
+        lib.sr3d_autotune.restype = ci
+        lib.sr3d_tune_save.argtypes = [ctypes.c_char_p]
+        lib.sr3d_tune_save.restype = ci
+        lib.sr3d_tune_load.argtypes = [ctypes.c_char_p]
+        lib.sr3d_tune_load.restype = ci
         lib.sr3d_profile_read.argtypes = [ci, ctypes.POINTER(ctypes.c_char_p),
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_long)]
@@ -278,6 +285,29 @@ def irfft3d(spec, shape, stream=None):
     out = torch.empty(tuple(shape), dtype=torch.float32, device=spec.device)
     _check(load().sr3d_irfft3d(dims_of(shape), _ptr(sp), _ptr(out), _stream(stream)))
     return out
+
+
+def autotune(shapes_rates, force=False, stream=None):
+    """Tune the FFT tile variants for HR shapes (s, n, m) with their rates
+    [(shape, rate), ...] (and the LR sizes they imply)."""
+    ps = []
+    for shape, rate in shapes_rates:
+        p = Problem()
+        p.hr, p.rate, p.psf_dims = dims_of(shape), rate_of(rate), Dims(1, 1, 1)
+        ps.append(p)
+    arr = (Problem * len(ps))(*ps)
+    _check(load().sr3d_autotune(arr, len(ps), int(bool(force)), _stream(stream)))
+
+
+def tune_save(path):
+    _check(load().sr3d_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    rc = load().sr3d_tune_load(str(path).encode())
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 def profile_reset():

@@ -66,6 +66,36 @@ def test_rfft3d_matches_numpy(shape):
     assert np.linalg.norm(back - x) / np.linalg.norm(x) < 2e-6
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_fft_tile_variant_is_correct(variant, tmp_path):
+    """Force one tile variant for every kind and length, check the transforms."""
+    f = tmp_path / "tiles.txt"
+    f.write_text("".join(f"{k} {L} {variant}\n" for k in range(6) for L in LENGTHS))
+    assert sr3d.tune_load(f) == 6 * len(LENGTHS)
+    try:
+        for shape in [(24, 48, 32), (8, 96, 64), (64, 64, 64), (3, 768, 6), (1024, 3, 4),
+                      (4, 3, 1024), (12, 6, 3)]:
+            rng = np.random.default_rng(sum(shape) + variant)
+            x = f32(rng.standard_normal(shape))
+            X = sr3d.rfft3d(dev(x))
+            ref = np.fft.rfftn(x)
+            got = X.cpu().numpy().astype(np.complex128)
+            assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 2e-6, shape
+            back = host(sr3d.irfft3d(X, shape))
+            assert np.linalg.norm(back - x) / np.linalg.norm(x) < 2e-6, shape
+    finally:
+        f.write_text("".join(f"{k} {L} 1\n" for k in range(6) for L in LENGTHS))
+        sr3d.tune_load(f)
+
+
+def test_autotune_runs_and_keeps_results_correct():
+    sr3d.autotune([((32, 48, 64), (2, 2, 4)), ((16, 16, 16), (2, 2, 2))], force=True)
+    y, psf, _ = problem((32, 48, 64), (2, 2, 4), 1.2, 0.02, 3)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), (2, 2, 4), LAM_TV, MU, 5)
+    ref = O.admm_tv(y, psf, (2, 2, 4), LAM_TV, MU, 5)
+    assert O.rel_l2(host(x), ref.x) < TOL
+
+
 def test_rfft3d_matches_bruteforce_dft():
     rng = np.random.default_rng(3)
     shape = (3, 4, 6)
