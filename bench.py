@@ -122,11 +122,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
+    ap.add_argument("--workload", default="tv256", choices=["tv256", "batch64"],
+                    help="tv256: the headline single-volume solve; batch64: 64 uneven volumes, "
+                         "sequential single solves vs one batched solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the workload is one volume; see the sharding design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        return bench_batch64(args)
 
     import numpy as np
     import torch
@@ -211,6 +216,104 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+BATCH_SHAPES = [(64, 64, 64), (64, 96, 96), (128, 128, 128), (96, 192, 192)]  # (s, n, m)
+BATCH_RATES = [(2, 2, 2), (2, 2, 4), (4, 4, 2)]                               # (dr, dc, ds)
+
+
+def batch64_problems(torch, sr3d, phantom, dev, count=64, seed0=100):
+    """64 volumes: shape, rate and sigma ~ U[0.8, 2.0] drawn per volume from
+    numpy.random.default_rng(seed), then the phantom with the same seed."""
+    import numpy as np
+    probs = []
+    for i in range(count):
+        seed = seed0 + i
+        meta = np.random.default_rng(seed)
+        shape = BATCH_SHAPES[int(meta.integers(len(BATCH_SHAPES)))]
+        rate = BATCH_RATES[int(meta.integers(len(BATCH_RATES)))]
+        sigma = float(meta.uniform(0.8, 2.0))
+        p = phantom.make_problem(shape, rate, sigma, 0.02, seed)
+        psf = torch.from_numpy(p["psf"].astype("float32")).to(dev)
+        xt = torch.from_numpy(p["x_true"].astype("float32")).to(dev)
+        y = sr3d.degrade(xt, psf, rate)
+        y += torch.from_numpy(p["noise"].astype("float32")).to(dev)
+        del xt
+        probs.append(dict(y=y.contiguous(), psf=psf, rate=rate, lam=2e-3, mu=5e-2, tol=1e-4,
+                          max_iter=200, shape=shape, sigma=sigma,
+                          x=torch.empty(shape, dtype=torch.float32, device=dev)))
+    torch.cuda.synchronize()
+    return probs
+
+
+def bench_batch64(args):
+    """Batched form: 64 uneven volumes solved (a) one after another with the
+    plain single-volume solver and (b) together by sr3d_batch (HIP-graph
+    replay), to the same tolerance; reports both rates and the speedup."""
+    import numpy as np
+    import torch
+    from paper_2010_15491_amd import phantom, sr3d
+
+    sr3d.load()
+    dev = torch.device("cuda:0")
+    probs = batch64_problems(torch, sr3d, phantom, dev)
+    sr3d.autotune(sorted({(q["shape"], q["rate"]) for q in probs}))
+    nh = sum(int(np.prod(q["shape"])) for q in probs)
+    ws_single = torch.empty(max(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [sr3d._problem(
+        q["shape"], q["rate"], q["psf"], y=q["y"], x=q["x"])]) for q in probs),
+        dtype=torch.uint8, device=dev)
+    flags = sr3d.FP64_REDUCE
+
+    def sequential():
+        out = []
+        for q in probs:
+            _, st = sr3d.tv_admm(q["y"], q["psf"], q["rate"], q["lam"], q["mu"], q["max_iter"],
+                                 tol=q["tol"], flags=flags, out=q["x"], workspace=ws_single)
+            out.append(st)
+        return out
+
+    bflags = flags | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(8)
+    bps = [sr3d._problem(q["shape"], q["rate"], q["psf"], q["lam"], q["mu"], q["tol"],
+                         q["max_iter"], y=q["y"], x=q["x"]) for q in probs]
+    ws_batch = torch.empty(sr3d.workspace_bytes(sr3d.OP_BATCH, bps), dtype=torch.uint8, device=dev)
+
+    def batched():
+        _, sts = sr3d.batch(probs, flags=bflags, workspace=ws_batch)
+        return sts
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            res = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, res
+
+    reps = max(1, args.steps)
+    ms_seq, st_seq = timed(sequential, reps)
+    x_seq = [q["x"].clone() for q in probs]
+    ms_bat, st_bat = timed(batched, reps)
+    same_iters = sum(a.iters == b.iters for a, b in zip(st_seq, st_bat))
+    max_rel = max(float(torch.linalg.vector_norm(q["x"] - xs) / torch.linalg.vector_norm(xs))
+                  for q, xs in zip(probs, x_seq))
+    out = {
+        "metric": "HR voxels/s, 64 uneven TV-ADMM volumes to 1e-4 tol (batched vs sequential)",
+        "value": nh / (ms_bat / 1e3), "unit": "HR voxels/s", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": ms_bat, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64_uneven_tv_admm", "volumes": len(probs),
+                   "total_hr_voxels": nh, "shapes_snm": BATCH_SHAPES, "rates": BATCH_RATES,
+                   "iters_min": min(s.iters for s in st_bat),
+                   "iters_max": max(s.iters for s in st_bat),
+                   "converged": sum(s.converged for s in st_bat),
+                   "same_iters_as_sequential": same_iters, "max_rel_l2_vs_sequential": max_rel},
+        "sequential": {"value": nh / (ms_seq / 1e3), "ms_per_step": ms_seq},
+        "speedup_vs_sequential": ms_seq / ms_bat,
     }
     print(json.dumps(out), flush=True)
 

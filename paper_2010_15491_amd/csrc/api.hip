@@ -388,12 +388,358 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   return SR3D_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched solve: many volumes, every stage launched once per FFT-length (or
+// decimation-factor) class over a work list of (volume, tile) items.
+// ---------------------------------------------------------------------------
+
+struct BatchPlan {
+  struct Group {
+    int kind;     // 0..5 FFT kinds, 6 fold, 7 stencil
+    int key;      // FFT length / decimation factor
+    int variant;  // FFT tile variant
+    std::vector<int2> items;
+    size_t off;   // byte offset of the items in the device header
+  };
+  std::vector<Group> groups;
+};
+
+// Header bytes for `count` volumes and the given items.
+struct BatchHeader {
+  RowDesc *r2c, *c2r;
+  StridedDesc *fn, *in_, *fs, *is;
+  FoldArgs *fold;
+  BatchStencilDesc *sten;
+  ReduceDesc *red;
+  int *active;
+  int2 *items;
+  size_t bytes;
+};
+
+size_t batch_header(int count, size_t nitems, char *base, BatchHeader *H) {
+  Carve c{base, 0};
+  H->r2c = c.take<RowDesc>(count);
+  H->c2r = c.take<RowDesc>(count);
+  H->fn = c.take<StridedDesc>(count);
+  H->in_ = c.take<StridedDesc>(count);
+  H->fs = c.take<StridedDesc>(count);
+  H->is = c.take<StridedDesc>(count);
+  H->fold = c.take<FoldArgs>(count);
+  H->sten = c.take<BatchStencilDesc>(count);
+  H->red = c.take<ReduceDesc>(count);
+  H->active = c.take<int>(64);
+  H->items = c.take<int2>(nitems);
+  H->bytes = c.off + 256;
+  return H->bytes;
+}
+
+// Items of every (stage, class) group for volumes with geometries g.
+size_t batch_items(const std::vector<Geometry> &g, BatchPlan *plan) {
+  plan->groups.clear();
+  auto group = [&](int kind, int key, int variant) -> BatchPlan::Group & {
+    for (auto &x : plan->groups)
+      if (x.kind == kind && x.key == key && x.variant == variant) return x;
+    plan->groups.push_back(BatchPlan::Group{kind, key, variant, {}, 0});
+    return plan->groups.back();
+  };
+  const int n = (int)g.size();
+  for (int kind = 0; kind < kFftKinds; ++kind) {
+    for (int v = 0; v < n; ++v) {
+      const Geometry &G = g[v];
+      const long Mh = G.Mh;
+      int len, tiles;
+      if (kind == kFftR2cM || kind == kFftC2rM) {
+        len = G.M;
+        if (len == 1) continue;  // copy kernels, launched per volume
+        tiles = row_tiles(len, fft_variant(kind, len), (long)G.S * G.N);
+      } else if (kind == kFftFwdN || kind == kFftInvN) {
+        len = G.N;
+        if (len == 1) continue;
+        tiles = strided_tiles(len, fft_variant(kind, len), (long)G.S * Mh);
+      } else {
+        len = G.S;
+        if (len == 1) continue;
+        tiles = strided_tiles(len, fft_variant(kind, len), (long)G.N * Mh);
+      }
+      auto &gr = group(kind, len, fft_variant(kind, len));
+      for (int t = 0; t < tiles; ++t) gr.items.push_back(make_int2(v, t));
+    }
+  }
+  for (int v = 0; v < n; ++v) {
+    FoldArgs fa = make_fold(g[v]);
+    auto &gr = group(6, g[v].D, 0);
+    const int nb = fold_blocks(fa);
+    for (int t = 0; t < nb; ++t) gr.items.push_back(make_int2(v, t));
+  }
+  {
+    auto &gr = group(7, 0, 0);
+    for (int v = 0; v < n; ++v) {
+      const int nb = stencil_plan(g[v].S, g[v].N, g[v].M).blocks;
+      for (int t = 0; t < nb; ++t) gr.items.push_back(make_int2(v, t));
+    }
+  }
+  size_t total = 0;
+  for (auto &x : plan->groups) total += x.items.size();
+  return total;
+}
+
+size_t batch_workspace(const sr3d_problem *p, int count, std::vector<Geometry> *gs,
+                       std::vector<size_t> *offs, BatchPlan *plan, size_t *header) {
+  gs->resize(count);
+  for (int i = 0; i < count; ++i)
+    if (check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &(*gs)[i])) return 0;
+  const size_t nitems = batch_items(*gs, plan);
+  BatchHeader H;
+  *header = batch_header(count, nitems, nullptr, &H);
+  size_t off = (*header + 255) & ~(size_t)255;
+  offs->resize(count);
+  for (int i = 0; i < count; ++i) {
+    TvWs L;
+    (*offs)[i] = off;
+    off += (tv_layout((*gs)[i], nullptr, &L) + 255) & ~(size_t)255;
+  }
+  return off;
+}
+
+hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
+                           const std::vector<Geometry> &g, const std::vector<TvWs> &Ls,
+                           const sr3d_problem *p, int k, bool fp64, hipStream_t st) {
+  const int n = (int)g.size();
+  hipError_t e = hipSuccess;
+  auto items_of = [&](const BatchPlan::Group &gr) {
+    return reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(H.items) + gr.off);
+  };
+  auto run_fft = [&](int kind, int stage) -> hipError_t {
+    for (auto &gr : plan.groups) {
+      if (gr.kind != kind) continue;
+      prof_begin(stage, st);
+      hipError_t r;
+      const int ni = (int)gr.items.size();
+      switch (kind) {
+        case kFftR2cM: r = launch_rows_batch(gr.key, false, gr.variant, H.r2c, items_of(gr), ni, st); break;
+        case kFftC2rM: r = launch_rows_batch(gr.key, true, gr.variant, H.c2r, items_of(gr), ni, st); break;
+        case kFftFwdN: r = launch_strided_batch(gr.key, false, gr.variant, H.fn, items_of(gr), ni, st); break;
+        case kFftInvN: r = launch_strided_batch(gr.key, true, gr.variant, H.in_, items_of(gr), ni, st); break;
+        case kFftFwdS: r = launch_strided_batch(gr.key, false, gr.variant, H.fs, items_of(gr), ni, st); break;
+        default: r = launch_strided_batch(gr.key, true, gr.variant, H.is, items_of(gr), ni, st); break;
+      }
+      prof_end(st);
+      if (r != hipSuccess) return r;
+    }
+    // volumes with m = 1 use the per-volume copy kernels
+    if (kind == kFftR2cM || kind == kFftC2rM)
+      for (int v = 0; v < n; ++v) {
+        if (g[v].M != 1) continue;
+        const Geometry &G = g[v];
+        hipError_t r = (kind == kFftR2cM)
+                           ? launch_r2c_m_v(Ls[v].theta, Ls[v].w, (long)G.S * G.N, 1, 0, &Ls[v].ctrl->done, st)
+                           : launch_c2r_m_v(Ls[v].w2, p[v].x, (long)G.S * G.N, 1, 1.0f, 0, &Ls[v].ctrl->done, st);
+        if (r != hipSuccess) return r;
+      }
+    return hipSuccess;
+  };
+  if ((e = run_fft(kFftR2cM, kStFftR2cM))) return e;
+  if ((e = run_fft(kFftFwdN, kStFftN))) return e;
+  if ((e = run_fft(kFftFwdS, kStFftS))) return e;
+  for (auto &gr : plan.groups) {
+    if (gr.kind != 6) continue;
+    prof_begin(kStFold, st);
+    e = fold_solve_batch(gr.key, H.fold, items_of(gr), (int)gr.items.size(), fp64, st);
+    prof_end(st);
+    if (e) return e;
+  }
+  if ((e = run_fft(kFftInvS, kStIfftS))) return e;
+  if ((e = run_fft(kFftInvN, kStIfftN))) return e;
+  if ((e = run_fft(kFftC2rM, kStIfftC2rM))) return e;
+  for (auto &gr : plan.groups) {
+    if (gr.kind != 7) continue;
+    prof_begin(kStStencil, st);
+    e = admm_stencil_batch(H.sten, items_of(gr), (int)gr.items.size(), k, fp64, st);
+    prof_end(st);
+    if (e) return e;
+  }
+  prof_begin(kStReduce, st);
+  e = reduce_and_test_batch(H.red, n, H.active, fp64, st);
+  prof_end(st);
+  return e;
+}
+
+int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
+              size_t ws_bytes, hipStream_t st) {
+  if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
+  Geometry g0;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_problem(&p[i], flags, &g0);
+    if (rc) return rc;
+  }
+  std::vector<Geometry> g;
+  std::vector<size_t> offs;
+  BatchPlan plan;
+  size_t hdr = 0;
+  const size_t need = batch_workspace(p, count, &g, &offs, &plan, &hdr);
+  if (!need) return fail(SR3D_ERR_INVALID_ARG, "invalid geometry");
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  char *base = reinterpret_cast<char *>(ws);
+  BatchHeader H;
+  size_t nitems = 0;
+  for (auto &gr : plan.groups) nitems += gr.items.size();
+  batch_header(count, nitems, base, &H);
+  std::vector<TvWs> Ls(count);
+  for (int i = 0; i < count; ++i) tv_layout(g[i], base + offs[i], &Ls[i]);
+  Ctrl *hc = host_ctrl();
+  if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  const bool fp64 = (flags & SR3D_FP64_REDUCE) != 0;
+  ProfScope prof((flags & SR3D_PROFILE) && !(flags & SR3D_USE_GRAPH));
+
+  // Host images of the descriptors and items.
+  std::vector<RowDesc> r2c(count), c2r(count);
+  std::vector<StridedDesc> fn(count), in_(count), fs(count), is(count);
+  std::vector<FoldArgs> fold(count);
+  std::vector<BatchStencilDesc> sten(count);
+  std::vector<ReduceDesc> red(count);
+  std::vector<float *> nu0(count);
+  for (int v = 0; v < count; ++v) {
+    const Geometry &G = g[v];
+    const TvWs &L = Ls[v];
+    const int *done = &L.ctrl->done;
+    const long Mh = G.Mh;
+    nu0[v] = p[v].state ? p[v].state : L.nu[0];
+    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done};
+    c2r[v] = RowDesc{nullptr, L.w2, p[v].x, (long)G.S * G.N, 1.0f, done};
+    fn[v] = make_strided_desc(L.w, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
+    in_[v] = make_strided_desc(L.w2, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
+    fs[v] = make_strided_desc(L.w, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
+    is[v] = make_strided_desc(L.w2, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
+    FoldArgs fa = make_fold(G);
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.gm = L.g; fa.gn = L.g + G.M; fa.gs = L.g + G.M + G.N;
+    fa.cw = p[v].mu; fa.coefA = p[v].mu; fa.tv = 1;
+    fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+    fold[v] = fa;
+    BatchStencilDesc sd{};
+    sd.a.x = p[v].x; sd.a.theta = L.theta;
+    sd.a.S = G.S; sd.a.N = G.N; sd.a.M = G.M; sd.a.thr = p[v].lambda_tv / p[v].mu;
+    sd.a.part = L.partS; sd.a.done = done;
+    sd.nu[0] = nu0[v];
+    sd.nu[1] = L.nu[1];
+    sd.pl = stencil_plan(G.S, G.N, G.M);
+    sten[v] = sd;
+    red[v] = ReduceDesc{L.ctrl, L.partS, L.nbS, L.partF, L.nbF};
+  }
+  std::vector<int2> items;
+  items.reserve(nitems);
+  for (auto &gr : plan.groups) {
+    gr.off = items.size() * sizeof(int2);
+    items.insert(items.end(), gr.items.begin(), gr.items.end());
+  }
+  std::vector<char> himg(hdr, 0);
+  auto put = [&](void *dst, const void *src, size_t bytes) {
+    memcpy(himg.data() + (reinterpret_cast<char *>(dst) - base), src, bytes);
+  };
+  put(H.r2c, r2c.data(), sizeof(RowDesc) * count);
+  put(H.c2r, c2r.data(), sizeof(RowDesc) * count);
+  put(H.fn, fn.data(), sizeof(StridedDesc) * count);
+  put(H.in_, in_.data(), sizeof(StridedDesc) * count);
+  put(H.fs, fs.data(), sizeof(StridedDesc) * count);
+  put(H.is, is.data(), sizeof(StridedDesc) * count);
+  put(H.fold, fold.data(), sizeof(FoldArgs) * count);
+  put(H.sten, sten.data(), sizeof(BatchStencilDesc) * count);
+  put(H.red, red.data(), sizeof(ReduceDesc) * count);
+  int active0 = count;
+  put(H.active, &active0, sizeof(int));
+  if (!items.empty()) put(H.items, items.data(), sizeof(int2) * items.size());
+  SR3D_TRY(hipMemcpyAsync(base, himg.data(), hdr, hipMemcpyHostToDevice, st), "batch header");
+
+  t_prof.override_stage = prof.on ? kStSetup : -1;
+  for (int v = 0; v < count; ++v) SR3D_TRY(tv_setup(g[v], Ls[v], &p[v], nu0[v], flags, st), "batch setup");
+  t_prof.override_stage = -1;
+  int max_iter = 0;
+  for (int v = 0; v < count; ++v) max_iter = p[v].max_iter > max_iter ? p[v].max_iter : max_iter;
+
+  int K = check_interval(flags);
+  int *h_active = reinterpret_cast<int *>(hc);
+  if (flags & SR3D_USE_GRAPH) {
+    K += K & 1;
+    hipStream_t cs;
+    SR3D_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream create");
+    hipEvent_t ev;
+    SR3D_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int i = 1; e == hipSuccess && i <= K; ++i)
+      e = batch_iteration(plan, H, g, Ls, p, i, fp64, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+    for (int it = 0; e == hipSuccess && it < max_iter; it += K) {
+      e = hipGraphLaunch(exec, cs);
+      if (e == hipSuccess) e = hipMemcpyAsync(h_active, H.active, sizeof(int), hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipStreamSynchronize(cs);
+      if (e == hipSuccess && *h_active <= 0) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipEventRecord(ev, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    (void)hipStreamSynchronize(cs);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "batch graph replay");
+  } else {
+    for (int it = 0; it < max_iter;) {
+      const int n = (max_iter - it) < K ? (max_iter - it) : K;
+      for (int i = 1; i <= n; ++i)
+        SR3D_TRY(batch_iteration(plan, H, g, Ls, p, it + i, fp64, st), "batch iteration");
+      it += n;
+      SR3D_TRY(hipMemcpyAsync(h_active, H.active, sizeof(int), hipMemcpyDeviceToHost, st), "active copy");
+      SR3D_TRY(hipStreamSynchronize(st), "stream sync");
+      if (prof.on) prof_flush();
+      if (*h_active <= 0) break;
+    }
+  }
+  // Per-volume results.
+  int status = SR3D_OK;
+  for (int v = 0; v < count; ++v) {
+    SR3D_TRY(hipMemcpyAsync(hc, Ls[v].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
+    SR3D_TRY(hipStreamSynchronize(st), "stream sync");
+    if (stats) {
+      stats[v].iters = hc->iter;
+      stats[v].converged = hc->converged;
+      stats[v].primal_rel = hc->primal_rel;
+      stats[v].dual_rel = hc->dual_rel;
+      stats[v].objective = hc->objective;
+    }
+    if (hc->status && !status) status = hc->status;
+    if (p[v].state && (hc->iter & 1)) {
+      SR3D_TRY(hipMemcpyAsync(p[v].state, Ls[v].nu[1], sizeof(float) * 3 * (size_t)g[v].NH,
+                              hipMemcpyDeviceToDevice, st), "state copy");
+    }
+  }
+  SR3D_TRY(hipStreamSynchronize(st), "stream sync");
+  if (status)
+    return fail(status, status == SR3D_ERR_SINGULAR ? "Lambda(0) = 0 in a batch volume"
+                                                    : "non-finite residual in a batch volume");
+  return SR3D_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
   if (!p || count < 1) return 0;
+  if (op == SR3D_OP_BATCH) {
+    std::vector<Geometry> gs;
+    std::vector<size_t> offs;
+    BatchPlan plan;
+    size_t hdr = 0;
+    return batch_workspace(p, count, &gs, &offs, &plan, &hdr);
+  }
   Geometry g;
   size_t total = 0;
   const int n = (op == SR3D_OP_BATCH) ? count : 1;
@@ -453,17 +799,7 @@ int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, 
 
 int sr3d_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
                size_t ws_bytes, hipStream_t st) {
-  if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
-  Geometry g;
-  for (int i = 0; i < count; ++i) {
-    int rc = check_problem(&p[i], flags, &g);
-    if (rc) return rc;
-  }
-  for (int i = 0; i < count; ++i) {
-    int rc = run_tv(&p[i], flags, stats ? &stats[i] : nullptr, ws, ws_bytes, st);
-    if (rc) return rc;
-  }
-  return SR3D_OK;
+  return run_batch(p, count, flags, stats, ws, ws_bytes, st);
 }
 
 int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf, sr3d_dims psf_dims,

@@ -12,18 +12,15 @@
 namespace sr3d {
 
 template <int M, int E>
-__global__ __launch_bounds__(kThreads) void k_r2c_half(const float *__restrict__ in,
-                                                       float2 *__restrict__ out, int nrows,
-                                                       const float2 *__restrict__ twh,
-                                                       const float2 *__restrict__ twm,
-                                                       const int *__restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
+                                              const float2 *__restrict__ twh,
+                                              const float2 *__restrict__ twm, float2 *lds,
+                                              float2 *stw) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
-  __shared__ float2 lds[H * TP];
-  __shared__ float2 stw[H];
-  const long row0 = (long)blockIdx.x * T;
+  const long row0 = (long)bid * T;
+  const long nrows = d.nrows;
   stage_twiddles<H>(stw, twh);
-  const float2 *in2 = reinterpret_cast<const float2 *>(in);
+  const float2 *in2 = reinterpret_cast<const float2 *>(d.rin);
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int i = w % H, t = w / H;
     const long r = row0 + t;
@@ -31,6 +28,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_half(const float *__restrict__
   }
   __syncthreads();
   fft_passes<H, T, TP, 0, 1>(lds, stw);
+  float2 *out = d.spec;
   for (int w = threadIdx.x; w < MH * T; w += kThreads) {
     const int k = w % MH, t = w / MH;
     const long r = row0 + t;
@@ -47,17 +45,14 @@ __global__ __launch_bounds__(kThreads) void k_r2c_half(const float *__restrict__
 }
 
 template <int M, int E>
-__global__ __launch_bounds__(kThreads) void k_c2r_half(const float2 *__restrict__ in,
-                                                       float *__restrict__ out, int nrows,
-                                                       float scale,
-                                                       const float2 *__restrict__ twh,
-                                                       const float2 *__restrict__ twm,
-                                                       const int *__restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
+                                              const float2 *__restrict__ twh,
+                                              const float2 *__restrict__ twm, float2 *lds,
+                                              float2 *stw) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
-  __shared__ float2 lds[H * TP];
-  __shared__ float2 stw[H];
-  const long row0 = (long)blockIdx.x * T;
+  const long row0 = (long)bid * T;
+  const long nrows = d.nrows;
+  const float2 *in = d.spec;
   stage_twiddles<H>(stw, twh);
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int k = w % H, t = w / H;
@@ -79,8 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_c2r_half(const float2 *__restrict_
   __syncthreads();
   fft_passes<H, T, TP, 0, 1>(lds, stw);
   // The unnormalised length-M inverse equals twice the length-M/2 one.
-  const float s2 = 2.0f * scale;
-  float2 *out2 = reinterpret_cast<float2 *>(out);
+  const float s2 = 2.0f * d.scale;
+  float2 *out2 = reinterpret_cast<float2 *>(d.rout);
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int i = w % H, t = w / H;
     const long r = row0 + t;
@@ -93,41 +88,34 @@ __global__ __launch_bounds__(kThreads) void k_c2r_half(const float2 *__restrict_
 
 // Odd lengths: the real row transformed as a complex one.
 template <int M, int E>
-__global__ __launch_bounds__(kThreads) void k_r2c_full(const float *__restrict__ in,
-                                                       float2 *__restrict__ out, int nrows,
-                                                       const float2 *__restrict__ tw,
-                                                       const int *__restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void r2c_full_body(const RowDesc &d, int bid,
+                                              const float2 *__restrict__ tw, float2 *lds,
+                                              float2 *stw) {
   constexpr int T = tile_lines(M, E), TP = T + 1, MH = M / 2 + 1;
-  __shared__ float2 lds[M * TP];
-  __shared__ float2 stw[M];
-  const long row0 = (long)blockIdx.x * T;
+  const long row0 = (long)bid * T;
+  const long nrows = d.nrows;
   stage_twiddles<M>(stw, tw);
   for (int w = threadIdx.x; w < M * T; w += kThreads) {
     const int i = w % M, t = w / M;
     const long r = row0 + t;
-    lds[i * TP + t] = make_float2((r < nrows) ? in[r * M + i] : 0.f, 0.f);
+    lds[i * TP + t] = make_float2((r < nrows) ? d.rin[r * M + i] : 0.f, 0.f);
   }
   __syncthreads();
   fft_passes<M, T, TP, 0, 1>(lds, stw);
   for (int w = threadIdx.x; w < MH * T; w += kThreads) {
     const int k = w % MH, t = w / MH;
     const long r = row0 + t;
-    if (r < nrows) out[r * MH + k] = lds[k * TP + t];
+    if (r < nrows) d.spec[r * MH + k] = lds[k * TP + t];
   }
 }
 
 template <int M, int E>
-__global__ __launch_bounds__(kThreads) void k_c2r_full(const float2 *__restrict__ in,
-                                                       float *__restrict__ out, int nrows,
-                                                       float scale,
-                                                       const float2 *__restrict__ tw,
-                                                       const int *__restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void c2r_full_body(const RowDesc &d, int bid,
+                                              const float2 *__restrict__ tw, float2 *lds,
+                                              float2 *stw) {
   constexpr int T = tile_lines(M, E), TP = T + 1, MH = M / 2 + 1;
-  __shared__ float2 lds[M * TP];
-  __shared__ float2 stw[M];
-  const long row0 = (long)blockIdx.x * T;
+  const long row0 = (long)bid * T;
+  const long nrows = d.nrows;
   stage_twiddles<M>(stw, tw);
   for (int w = threadIdx.x; w < M * T; w += kThreads) {
     const int k = w % M, t = w / M;
@@ -135,10 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_c2r_full(const float2 *__restrict_
     float2 v = make_float2(0.f, 0.f);
     if (r < nrows) {
       if (k < MH) {
-        v = in[r * MH + k];
+        v = d.spec[r * MH + k];
         v.y = -v.y;
       } else {
-        v = in[r * MH + (M - k)];
+        v = d.spec[r * MH + (M - k)];
       }
     }
     lds[k * TP + t] = v;
@@ -148,8 +136,45 @@ __global__ __launch_bounds__(kThreads) void k_c2r_full(const float2 *__restrict_
   for (int w = threadIdx.x; w < M * T; w += kThreads) {
     const int i = w % M, t = w / M;
     const long r = row0 + t;
-    if (r < nrows) out[r * M + i] = lds[i * TP + t].x * scale;
+    if (r < nrows) d.rout[r * M + i] = lds[i * TP + t].x * d.scale;
   }
+}
+
+// Kernels: single volume (blockIdx = row tile) and batch (item = volume, tile).
+template <int M, int E, bool C2R>
+__device__ __forceinline__ void row_body(const RowDesc &d, int bid, const float2 *twh,
+                                         const float2 *twm) {
+  if constexpr (M % 2 == 0) {
+    constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1;
+    __shared__ float2 lds[H * TP];
+    __shared__ float2 stw[H];
+    if (C2R) c2r_half_body<M, E>(d, bid, twh, twm, lds, stw);
+    else r2c_half_body<M, E>(d, bid, twh, twm, lds, stw);
+  } else {
+    constexpr int T = tile_lines(M, E), TP = T + 1;
+    __shared__ float2 lds[M * TP];
+    __shared__ float2 stw[M];
+    if (C2R) c2r_full_body<M, E>(d, bid, twm, lds, stw);
+    else r2c_full_body<M, E>(d, bid, twm, lds, stw);
+  }
+}
+
+template <int M, int E, bool C2R>
+__global__ __launch_bounds__(kThreads) void k_fft_rows(RowDesc d, const float2 *__restrict__ twh,
+                                                       const float2 *__restrict__ twm) {
+  if (d.done && *d.done) return;
+  row_body<M, E, C2R>(d, blockIdx.x, twh, twm);
+}
+
+template <int M, int E, bool C2R>
+__global__ __launch_bounds__(kThreads) void k_fft_rows_batch(const RowDesc *__restrict__ descs,
+                                                             const int2 *__restrict__ items,
+                                                             const float2 *__restrict__ twh,
+                                                             const float2 *__restrict__ twm) {
+  const int2 it = items[blockIdx.x];
+  const RowDesc d = descs[it.x];
+  if (d.done && *d.done) return;
+  row_body<M, E, C2R>(d, it.y, twh, twm);
 }
 
 // Length-1 axis m: copy with zero imaginary part / take the real part.
@@ -168,32 +193,74 @@ __global__ void k_copy_c2r1(const float2 *in, float *out, long n, float scale, c
   X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) \
   X(512) X(768) X(1024)
 
-template <int M, int E>
-static void launch_r2c_t(const float *in, float2 *out, long nrows, const int *done,
-                         hipStream_t st) {
-  if constexpr (M % 2 == 0) {
-    constexpr int T = tile_lines(M / 2, E);
-    hipLaunchKernelGGL((k_r2c_half<M, E>), dim3((unsigned)((nrows + T - 1) / T)), dim3(kThreads),
-                       0, st, in, out, (int)nrows, twiddles(M / 2), twiddles(M), done);
-  } else {
-    constexpr int T = tile_lines(M, E);
-    hipLaunchKernelGGL((k_r2c_full<M, E>), dim3((unsigned)((nrows + T - 1) / T)), dim3(kThreads),
-                       0, st, in, out, (int)nrows, twiddles(M), done);
-  }
+constexpr int row_tile_lines(int M, int E) {
+  return (M % 2 == 0) ? tile_lines(M / 2, E) : tile_lines(M, E);
 }
 
 template <int M, int E>
-static void launch_c2r_t(const float2 *in, float *out, long nrows, float scale, const int *done,
-                         hipStream_t st) {
-  if constexpr (M % 2 == 0) {
-    constexpr int T = tile_lines(M / 2, E);
-    hipLaunchKernelGGL((k_c2r_half<M, E>), dim3((unsigned)((nrows + T - 1) / T)), dim3(kThreads),
-                       0, st, in, out, (int)nrows, scale, twiddles(M / 2), twiddles(M), done);
-  } else {
-    constexpr int T = tile_lines(M, E);
-    hipLaunchKernelGGL((k_c2r_full<M, E>), dim3((unsigned)((nrows + T - 1) / T)), dim3(kThreads),
-                       0, st, in, out, (int)nrows, scale, twiddles(M), done);
+static void launch_rows_t(const RowDesc &d, bool c2r, hipStream_t st) {
+  constexpr int T = row_tile_lines(M, E);
+  const float2 *twh = (M % 2 == 0) ? twiddles(M / 2) : nullptr;
+  dim3 g((unsigned)((d.nrows + T - 1) / T));
+  if (c2r) hipLaunchKernelGGL((k_fft_rows<M, E, true>), g, dim3(kThreads), 0, st, d, twh, twiddles(M));
+  else hipLaunchKernelGGL((k_fft_rows<M, E, false>), g, dim3(kThreads), 0, st, d, twh, twiddles(M));
+}
+
+template <int M, int E>
+static void launch_rows_batch_t(const RowDesc *descs, const int2 *items, int nitems, bool c2r,
+                                hipStream_t st) {
+  const float2 *twh = (M % 2 == 0) ? twiddles(M / 2) : nullptr;
+  if (c2r)
+    hipLaunchKernelGGL((k_fft_rows_batch<M, E, true>), dim3(nitems), dim3(kThreads), 0, st, descs,
+                       items, twh, twiddles(M));
+  else
+    hipLaunchKernelGGL((k_fft_rows_batch<M, E, false>), dim3(nitems), dim3(kThreads), 0, st, descs,
+                       items, twh, twiddles(M));
+}
+
+int row_tiles(int M, int v, long nrows) {
+  const int L = (M % 2 == 0) ? M / 2 : M;
+  int T = 1;
+  while (T < 64 && 2 * T * L <= kTileElems[v < 0 ? 0 : v > 2 ? 2 : v]) T *= 2;
+  return (int)((nrows + T - 1) / T);
+}
+
+static hipError_t launch_rows(const RowDesc &d, int M, bool c2r, int v, hipStream_t st) {
+  if (!twiddles(M) || (M % 2 == 0 && !twiddles(M / 2))) return hipErrorInvalidValue;
+  switch (M) {
+#define SR3D_CASE(L)                                          \
+  case L:                                                     \
+    if (v == 0) launch_rows_t<L, kTileElems[0]>(d, c2r, st);  \
+    else if (v == 1) launch_rows_t<L, kTileElems[1]>(d, c2r, st); \
+    else launch_rows_t<L, kTileElems[2]>(d, c2r, st);         \
+    break;
+    SR3D_EVEN_M(SR3D_CASE)
+    SR3D_CASE(3)
+#undef SR3D_CASE
+    default:
+      return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const int2 *items,
+                             int nitems, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  if (M == 1 || !twiddles(M) || (M % 2 == 0 && !twiddles(M / 2))) return hipErrorInvalidValue;
+  switch (M) {
+#define SR3D_CASE(L)                                                              \
+  case L:                                                                         \
+    if (v == 0) launch_rows_batch_t<L, kTileElems[0]>(descs, items, nitems, c2r, st); \
+    else if (v == 1) launch_rows_batch_t<L, kTileElems[1]>(descs, items, nitems, c2r, st); \
+    else launch_rows_batch_t<L, kTileElems[2]>(descs, items, nitems, c2r, st);    \
+    break;
+    SR3D_EVEN_M(SR3D_CASE)
+    SR3D_CASE(3)
+#undef SR3D_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
@@ -203,21 +270,8 @@ hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v
                        out, nrows, done);
     return hipGetLastError();
   }
-  if (!twiddles(M)) return hipErrorInvalidValue;
-  switch (M) {
-#define SR3D_CASE(L)                                                         \
-  case L:                                                                    \
-    if (v == 0) launch_r2c_t<L, kTileElems[0]>(in, out, nrows, done, st);    \
-    else if (v == 1) launch_r2c_t<L, kTileElems[1]>(in, out, nrows, done, st); \
-    else launch_r2c_t<L, kTileElems[2]>(in, out, nrows, done, st);           \
-    break;
-    SR3D_EVEN_M(SR3D_CASE)
-    SR3D_CASE(3)
-#undef SR3D_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  RowDesc d{in, out, nullptr, nrows, 1.0f, done};
+  return launch_rows(d, M, false, v, st);
 }
 
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
@@ -227,21 +281,8 @@ hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float
                        out, nrows, scale, done);
     return hipGetLastError();
   }
-  if (!twiddles(M)) return hipErrorInvalidValue;
-  switch (M) {
-#define SR3D_CASE(L)                                                                \
-  case L:                                                                           \
-    if (v == 0) launch_c2r_t<L, kTileElems[0]>(in, out, nrows, scale, done, st);    \
-    else if (v == 1) launch_c2r_t<L, kTileElems[1]>(in, out, nrows, scale, done, st); \
-    else launch_c2r_t<L, kTileElems[2]>(in, out, nrows, scale, done, st);           \
-    break;
-    SR3D_EVEN_M(SR3D_CASE)
-    SR3D_CASE(3)
-#undef SR3D_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done};
+  return launch_rows(d, M, true, v, st);
 }
 
 }  // namespace sr3d

@@ -10,23 +10,20 @@
 namespace sr3d {
 
 template <int N, bool INV, int E>
-__global__ __launch_bounds__(kThreads) void k_fft_strided(float2 *__restrict__ data, int ncols,
-                                                          FastDiv inner, long outer_stride,
-                                                          long estride,
-                                                          const float2 *__restrict__ tw,
-                                                          const int *__restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void strided_body(const StridedDesc &d, int bid,
+                                             const float2 *__restrict__ tw, float2 *lds,
+                                             float2 *stw) {
   constexpr int T = tile_lines(N, E);
-  __shared__ float2 lds[N * T];
-  __shared__ float2 stw[N];
   const int t = threadIdx.x % T;  // fixed per thread since T divides kThreads
-  const int c = blockIdx.x * T + t;
-  const bool valid = c < ncols;
+  const int c = bid * T + t;
+  const bool valid = c < d.ncols;
   long base = 0;
   if (valid) {
-    const uint32_t q = inner.div((uint32_t)c);
-    base = (long)q * outer_stride + (long)(c - q * inner.d);
+    const uint32_t q = d.inner.div((uint32_t)c);
+    base = (long)q * d.outer_stride + (long)(c - q * d.inner.d);
   }
+  float2 *data = d.data;
+  const long estride = d.estride;
   stage_twiddles<N>(stw, tw);
   for (int w = threadIdx.x; w < N * T; w += kThreads) {
     const int i = w / T;
@@ -49,30 +46,91 @@ __global__ __launch_bounds__(kThreads) void k_fft_strided(float2 *__restrict__ d
   }
 }
 
+template <int N, bool INV, int E>
+__global__ __launch_bounds__(kThreads) void k_fft_strided(StridedDesc d,
+                                                          const float2 *__restrict__ tw) {
+  if (d.done && *d.done) return;
+  constexpr int T = tile_lines(N, E);
+  __shared__ float2 lds[N * T];
+  __shared__ float2 stw[N];
+  strided_body<N, INV, E>(d, blockIdx.x, tw, lds, stw);
+}
+
+// Many volumes with the same line length: item (volume, tile) per workgroup.
+template <int N, bool INV, int E>
+__global__ __launch_bounds__(kThreads) void k_fft_strided_batch(const StridedDesc *__restrict__ descs,
+                                                                const int2 *__restrict__ items,
+                                                                const float2 *__restrict__ tw) {
+  const int2 it = items[blockIdx.x];
+  const StridedDesc d = descs[it.x];
+  if (d.done && *d.done) return;
+  constexpr int T = tile_lines(N, E);
+  __shared__ float2 lds[N * T];
+  __shared__ float2 stw[N];
+  strided_body<N, INV, E>(d, it.y, tw, lds, stw);
+}
+
 template <int L, int E>
-static void launch_strided_t(float2 *data, long ncols, FastDiv fd, long outer_stride, long estride,
-                             bool inv, const int *done, hipStream_t st) {
+static void launch_strided_t(const StridedDesc &d, bool inv, hipStream_t st) {
   constexpr int T = tile_lines(L, E);
-  dim3 g((unsigned)((ncols + T - 1) / T));
+  dim3 g((unsigned)((d.ncols + T - 1) / T));
   if (inv)
-    hipLaunchKernelGGL((k_fft_strided<L, true, E>), g, dim3(kThreads), 0, st, data, (int)ncols, fd,
-                       outer_stride, estride, twiddles(L), done);
+    hipLaunchKernelGGL((k_fft_strided<L, true, E>), g, dim3(kThreads), 0, st, d, twiddles(L));
   else
-    hipLaunchKernelGGL((k_fft_strided<L, false, E>), g, dim3(kThreads), 0, st, data, (int)ncols,
-                       fd, outer_stride, estride, twiddles(L), done);
+    hipLaunchKernelGGL((k_fft_strided<L, false, E>), g, dim3(kThreads), 0, st, d, twiddles(L));
+}
+
+template <int L, int E>
+static void launch_strided_batch_t(const StridedDesc *descs, const int2 *items, int nitems, bool inv,
+                                   hipStream_t st) {
+  if (inv)
+    hipLaunchKernelGGL((k_fft_strided_batch<L, true, E>), dim3(nitems), dim3(kThreads), 0, st,
+                       descs, items, twiddles(L));
+  else
+    hipLaunchKernelGGL((k_fft_strided_batch<L, false, E>), dim3(nitems), dim3(kThreads), 0, st,
+                       descs, items, twiddles(L));
+}
+
+int strided_tiles(int L, int v, long ncols) {
+  int T = 1;
+  switch (v) {
+    case 0: T = 1; while (T < 64 && 2 * T * L <= kTileElems[0]) T *= 2; break;
+    case 1: T = 1; while (T < 64 && 2 * T * L <= kTileElems[1]) T *= 2; break;
+    default: T = 1; while (T < 64 && 2 * T * L <= kTileElems[2]) T *= 2; break;
+  }
+  return (int)((ncols + T - 1) / T);
+}
+
+hipError_t launch_strided_batch(int L, bool inv, int v, const StridedDesc *descs, const int2 *items,
+                                int nitems, hipStream_t st) {
+  if (L == 1 || nitems == 0) return hipSuccess;
+  if (!twiddles(L)) return hipErrorInvalidValue;
+  switch (L) {
+#define SR3D_CASE(LL)                                                                     \
+  case LL:                                                                                \
+    if (v == 0) launch_strided_batch_t<LL, kTileElems[0]>(descs, items, nitems, inv, st); \
+    else if (v == 1) launch_strided_batch_t<LL, kTileElems[1]>(descs, items, nitems, inv, st); \
+    else launch_strided_batch_t<LL, kTileElems[2]>(descs, items, nitems, inv, st);        \
+    break;
+    SR3D_FFT_LENGTHS(SR3D_CASE)
+#undef SR3D_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
                             long estride, bool inv, int v, const int *done, hipStream_t st) {
   if (L == 1) return hipSuccess;
   if (!twiddles(L)) return hipErrorInvalidValue;
-  FastDiv fd((uint32_t)inner);
+  const StridedDesc d = make_strided_desc(data, ncols, inner, outer_stride, estride, done);
   switch (L) {
-#define SR3D_CASE(LL)                                                                          \
-  case LL:                                                                                     \
-    if (v == 0) launch_strided_t<LL, kTileElems[0]>(data, ncols, fd, outer_stride, estride, inv, done, st); \
-    else if (v == 1) launch_strided_t<LL, kTileElems[1]>(data, ncols, fd, outer_stride, estride, inv, done, st); \
-    else launch_strided_t<LL, kTileElems[2]>(data, ncols, fd, outer_stride, estride, inv, done, st); \
+#define SR3D_CASE(LL)                                                           \
+  case LL:                                                                      \
+    if (v == 0) launch_strided_t<LL, kTileElems[0]>(d, inv, st);                \
+    else if (v == 1) launch_strided_t<LL, kTileElems[1]>(d, inv, st);           \
+    else launch_strided_t<LL, kTileElems[2]>(d, inv, st);                       \
     break;
     SR3D_FFT_LENGTHS(SR3D_CASE)
 #undef SR3D_CASE

@@ -51,11 +51,10 @@ __device__ __forceinline__ T block_reduce_sum(T v, T *sh) {
 }
 
 template <int D, typename Acc>
-__global__ __launch_bounds__(kThreads) void k_fold_solve(FoldArgs a) {
-  if (a.done && *a.done) return;
+__device__ __forceinline__ void fold_body(const FoldArgs &a, int bid) {
   __shared__ Acc sh[kThreads / 64];
   const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
-  const long g = (long)blockIdx.x * kThreads + threadIdx.x;
+  const long g = (long)bid * kThreads + threadIdx.x;
   Acc resid = 0;
   if (g < ngroups) {
     const int jm = (int)(g % a.ml_eff);
@@ -199,8 +198,23 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve(FoldArgs a) {
   }
   if (a.partial) {
     const Acc s = block_reduce_sum<Acc>(resid, sh);
-    if (threadIdx.x == 0) reinterpret_cast<Acc *>(a.partial)[blockIdx.x] = s;
+    if (threadIdx.x == 0) reinterpret_cast<Acc *>(a.partial)[bid] = s;
   }
+}
+
+template <int D, typename Acc>
+__global__ __launch_bounds__(kThreads) void k_fold_solve(FoldArgs a) {
+  if (a.done && *a.done) return;
+  fold_body<D, Acc>(a, blockIdx.x);
+}
+
+template <int D, typename Acc>
+__global__ __launch_bounds__(kThreads) void k_fold_solve_batch(const FoldArgs *__restrict__ descs,
+                                                               const int2 *__restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const FoldArgs a = descs[it.x];
+  if (a.done && *a.done) return;
+  fold_body<D, Acc>(a, it.y);
 }
 
 int fold_blocks(const FoldArgs &a) {
@@ -224,6 +238,31 @@ static hipError_t launch_fold(const FoldArgs &a, hipStream_t st) {
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename Acc>
+static hipError_t launch_fold_batch(int D, const FoldArgs *descs, const int2 *items, int nitems,
+                                    hipStream_t st) {
+  dim3 g((unsigned)nitems), b(kThreads);
+  switch (D) {
+#define SR3D_D(DD)                                                                 \
+  case DD:                                                                         \
+    hipLaunchKernelGGL((k_fold_solve_batch<DD, Acc>), g, b, 0, st, descs, items);  \
+    break;
+    SR3D_D(1) SR3D_D(2) SR3D_D(3) SR3D_D(4) SR3D_D(6) SR3D_D(8) SR3D_D(9) SR3D_D(12)
+    SR3D_D(16) SR3D_D(18) SR3D_D(24) SR3D_D(27) SR3D_D(32) SR3D_D(36) SR3D_D(48) SR3D_D(64)
+#undef SR3D_D
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t fold_solve_batch(int D, const FoldArgs *descs, const int2 *items, int nitems, bool fp64,
+                            hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  return fp64 ? launch_fold_batch<double>(D, descs, items, nitems, st)
+              : launch_fold_batch<float>(D, descs, items, nitems, st);
 }
 
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st) {

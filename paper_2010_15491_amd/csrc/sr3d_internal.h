@@ -19,7 +19,7 @@ struct Ctrl {
   int converged;  // tolerance test held
   int status;     // 0 or a negative sr3d_status found on the device
   int max_iter;
-  int pad0;
+  int counted;    // batch: this volume's stop has been counted
   float tol, mu, lam, pad1;
   double primal_rel, dual_rel, objective;
   double inv_nl;  // 1 / N_l (LR Parseval factor of the data term)
@@ -61,7 +61,41 @@ void prof_end(hipStream_t st);
 
 bool fft_len_supported(int n);
 
-// Axis kernels and their tile variants (fft_m.hip, fft_strided.hip).
+// Axis kernels and their tile variants (fft_m.hip, fft_strided.hip). A
+// descriptor holds one volume's arguments; batch launches take an array of
+// descriptors and a list of (volume, tile) items, one workgroup per item.
+struct StridedDesc {
+  float2 *data;
+  int ncols;
+  FastDiv inner;
+  long outer_stride, estride;
+  const int *done;
+};
+inline StridedDesc make_strided_desc(float2 *data, long ncols, long inner, long outer_stride,
+                                     long estride, const int *done) {
+  StridedDesc d;
+  d.data = data;
+  d.ncols = (int)ncols;
+  d.inner = FastDiv((uint32_t)inner);
+  d.outer_stride = outer_stride;
+  d.estride = estride;
+  d.done = done;
+  return d;
+}
+struct RowDesc {
+  const float *rin;  // R2C input rows
+  float2 *spec;      // half-spectrum rows (R2C output / C2R input)
+  float *rout;       // C2R output rows
+  long nrows;
+  float scale;       // C2R output scale
+  const int *done;
+};
+int strided_tiles(int L, int v, long ncols);
+int row_tiles(int M, int v, long nrows);
+hipError_t launch_strided_batch(int L, bool inv, int v, const StridedDesc *descs, const int2 *items,
+                                int nitems, hipStream_t st);
+hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const int2 *items,
+                             int nitems, hipStream_t st);
 enum FftKind { kFftR2cM, kFftC2rM, kFftFwdN, kFftInvN, kFftFwdS, kFftInvS, kFftKinds };
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
                           hipStream_t st);
@@ -110,6 +144,8 @@ struct FoldArgs {
 };
 int fold_blocks(const FoldArgs &a);
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
+hipError_t fold_solve_batch(int D, const FoldArgs *descs, const int2 *items, int nitems, bool fp64,
+                            hipStream_t st);
 
 // Fused difference / shrink / dual / Theta pass (Algorithm 1 steps 5b, 5c and
 // the Theta of the next 5a). State nu = L x + d_prev holds (u, d):
@@ -129,11 +165,27 @@ struct StencilPlan {
 };
 StencilPlan stencil_plan(int S, int N, int M);
 hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st);
+struct BatchStencilDesc {
+  AdmmStencilArgs a;
+  float *nu[2];
+  StencilPlan pl;
+};
+hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
+                              bool fp64, hipStream_t st);
 hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,
                          hipStream_t st);
 // Final reduction of the partial sums and the stopping test.
 hipError_t reduce_and_test(Ctrl *ctrl, const void *partS, int nbS, const void *partF, int nbF,
                            bool fp64, hipStream_t st);
+struct ReduceDesc {
+  Ctrl *ctrl;
+  const void *ps;
+  int nbs;
+  const void *pf;
+  int nbf;
+};
+hipError_t reduce_and_test_batch(const ReduceDesc *descs, int nvol, int *active, bool fp64,
+                                 hipStream_t st);
 
 // Setup kernels.
 hipError_t pad_psf(const float *psf, int Ks, int Kn, int Km, float *out, int S, int N, int M,

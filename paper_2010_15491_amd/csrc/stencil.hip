@@ -95,8 +95,8 @@ __device__ __forceinline__ void point_update(const float *xc, const float *xn, i
 }
 
 template <typename Acc, bool STATS>
-__global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, StencilPlan pl) {
-  if (a.done && *a.done) return;
+__device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const StencilPlan &pl, int b,
+                                             int slot) {
   __shared__ float xs[3][XR];
   __shared__ float fw[2][FF], fd[2][FF], fu[2][FF];  // m and n components at tile + faces
   __shared__ Acc sh[6 * 4];
@@ -104,7 +104,6 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, St
   const int S = a.S, N = a.N, M = a.M;
   const long NT = (long)S * N * M;
   const long plane = (long)N * M;
-  const int b = xcd_tile(blockIdx.x, pl.blocks);
   const int tm = b % pl.tiles_m;
   const int tn = (b / pl.tiles_m) % pl.tiles_n;
   const int ch = b / (pl.tiles_m * pl.tiles_n);
@@ -298,9 +297,29 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, St
     block_reduce_n<Acc>(acc, 6, sh);
     if (tid == 0) {
       Acc *p = reinterpret_cast<Acc *>(a.part);
-      for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + blockIdx.x] = acc[q];
+      for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + slot] = acc[q];
     }
   }
+}
+
+template <typename Acc, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, StencilPlan pl) {
+  if (a.done && *a.done) return;
+  stencil_body<Acc, STATS>(a, pl, xcd_tile(blockIdx.x, pl.blocks), blockIdx.x);
+}
+
+// Batch: item (volume, tile); iteration k reads nu[(k-1)&1] and writes nu[k&1].
+template <typename Acc>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil_batch(const BatchStencilDesc *__restrict__ descs,
+                                                                 const int2 *__restrict__ items,
+                                                                 int k) {
+  const int2 it = items[blockIdx.x];
+  const BatchStencilDesc d = descs[it.x];
+  if (d.a.done && *d.a.done) return;
+  AdmmStencilArgs a = d.a;
+  a.nu_in = d.nu[(k - 1) & 1];
+  a.nu_out = d.nu[k & 1];
+  stencil_body<Acc, true>(a, d.pl, it.y, it.y);
 }
 
 StencilPlan stencil_plan(int S, int N, int M) {
@@ -316,6 +335,18 @@ StencilPlan stencil_plan(int S, int N, int M) {
   p.chunks = (S + p.L - 1) / p.L;
   p.blocks = (int)(cols * p.chunks);
   return p;
+}
+
+hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
+                              bool fp64, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL((k_admm_stencil_batch<double>), dim3(nitems), dim3(kThreads), 0, st, descs,
+                       items, k);
+  else
+    hipLaunchKernelGGL((k_admm_stencil_batch<float>), dim3(nitems), dim3(kThreads), 0, st, descs,
+                       items, k);
+  return hipGetLastError();
 }
 
 hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st) {
@@ -383,9 +414,8 @@ hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, flo
 // Sums of the 6 stencil partial arrays and the fold partials, all loads of a
 // thread issued before any shuffle.
 template <typename Acc>
-__global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *ps, int nbs,
-                                                      const Acc *pf, int nbf) {
-  if (c->done) return;
+__device__ __forceinline__ void reduce_body(Ctrl *c, const Acc *ps, int nbs, const Acc *pf,
+                                            int nbf) {
   __shared__ Acc sh[7][16];
   Acc q[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < nbs; i += 1024) {
@@ -433,6 +463,40 @@ __global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *ps, in
     c->done = 1;
   }
   if (c->iter >= c->max_iter) c->done = 1;
+}
+
+template <typename Acc>
+__global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *ps, int nbs,
+                                                      const Acc *pf, int nbf) {
+  if (c->done) return;
+  reduce_body<Acc>(c, ps, nbs, pf, nbf);
+}
+
+// Batch: one workgroup per volume. When a volume stops (converged, capped or
+// failed, here or earlier in the fold), the count of active volumes drops by
+// one, exactly once per volume.
+template <typename Acc>
+__global__ __launch_bounds__(1024) void k_reduce_test_batch(const ReduceDesc *__restrict__ descs,
+                                                            int *active) {
+  const ReduceDesc d = descs[blockIdx.x];
+  Ctrl *c = d.ctrl;
+  if (!c->done) {
+    reduce_body<Acc>(c, (const Acc *)d.ps, d.nbs, (const Acc *)d.pf, d.nbf);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && c->done && !c->counted) {
+    c->counted = 1;
+    atomicSub(active, 1);
+  }
+}
+
+hipError_t reduce_and_test_batch(const ReduceDesc *descs, int nvol, int *active, bool fp64,
+                                 hipStream_t st) {
+  if (fp64)
+    hipLaunchKernelGGL(k_reduce_test_batch<double>, dim3(nvol), dim3(1024), 0, st, descs, active);
+  else
+    hipLaunchKernelGGL(k_reduce_test_batch<float>, dim3(nvol), dim3(1024), 0, st, descs, active);
+  return hipGetLastError();
 }
 
 hipError_t reduce_and_test(Ctrl *ctrl, const void *partS, int nbS, const void *partF, int nbF,
@@ -503,7 +567,7 @@ __global__ void k_ctrl_init(Ctrl *c, int max_iter, float tol, float mu, float la
   c->converged = 0;
   c->status = 0;
   c->max_iter = max_iter;
-  c->pad0 = 0;
+  c->counted = 0;
   c->tol = tol;
   c->mu = mu;
   c->lam = lam;

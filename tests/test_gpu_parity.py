@@ -292,6 +292,29 @@ def test_batch_matches_single_solves():
         assert O.rel_l2(host(x), ref) < TOL
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_uneven_volumes_stop_like_single_solves(graph):
+    """Uneven sizes and rates; each volume stops at its own iteration, exactly
+    as its single solve does, and returns the same x."""
+    cases = [((64, 64, 64), (2, 2, 2), 1.0), ((64, 96, 96), (4, 4, 2), 1.5),
+             ((32, 48, 48), (2, 2, 4), 0.8), ((32, 32, 32), (2, 2, 2), 2.0),
+             ((24, 12, 16), (1, 1, 1), 1.0)]
+    tol = 3e-2  # the oracle stops these at 47, 50, 46, >120 (cap) and 56 iterations
+    probs, singles = [], []
+    for i, (shape, rate, sig) in enumerate(cases):
+        y, psf, _ = problem(shape, rate, sig, 0.02, 200 + i, n_ell=6)
+        q = dict(y=dev(y), psf=dev(psf), rate=rate, lam=LAM_TV, mu=MU, max_iter=120, tol=tol)
+        probs.append(q)
+        singles.append(sr3d.tv_admm(q["y"], q["psf"], rate, LAM_TV, MU, 120, tol=tol))
+    flags = sr3d.FP64_REDUCE | (sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(4) if graph else 0)
+    xs, sts = sr3d.batch(probs, flags=flags)
+    iters = [st.iters for st in sts]
+    assert len(set(iters)) > 1, iters  # volumes really stop at different iterations
+    for x, st, (xs1, st1) in zip(xs, sts, singles):
+        assert st.iters == st1.iters and st.converged == st1.converged
+        assert O.rel_l2(host(x), host(xs1)) < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # Full size (256^3, the benchmark workload): first iterate against the oracle,
 # invariants after the benchmark's iterations.
