@@ -143,6 +143,51 @@ int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf,
 int sr3d_rfft3d(sr3d_dims dims, const float *in, float *spec, hipStream_t stream);
 int sr3d_irfft3d(sr3d_dims dims, float *spec, float *out, hipStream_t stream);
 
+/* Learned warm start (not in the paper): x0 = x + f(x) for Algorithm 1,
+ * where x is the Tikhonov solution (eq. (12)) and f a 3D CNN of six 3x3x3
+ * convolutions (1->32, four 32->32, 32->1 channels) with bias, ReLU after the
+ * first five and periodic padding. Tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) for
+ * offsets along (s, n, m); conv(a)[v][co] = sum_t sum_ci W[t][co][ci]
+ * a[v + off_t][ci] + b[co]. Parameters are one FP32 vector: per layer W as
+ * [27][cout][cin] then b[cout]. Weights and hidden activations are rounded to
+ * bfloat16 (nearest even; hidden activations stored channels-last,
+ * [voxel][32]); sums accumulate in FP32 on BF16 matrix cores. Loss: mean
+ * squared error against a target volume; optimiser: Adam on the FP32
+ * parameters. All pointers are device memory owned by the caller. */
+size_t sr3d_cnn_param_count(void);
+/* He-uniform weights (last layer scaled by 0.1), zero biases, from a
+ * counter-based generator (SplitMix64) seeded with `seed`. */
+int sr3d_cnn_init(float *params, unsigned long long seed, hipStream_t stream);
+/* Workspace for sr3d_cnn_forward (training = 0) or sr3d_cnn_grad (training = 1)
+ * on a volume of size dims. */
+size_t sr3d_cnn_workspace_size(sr3d_dims dims, int training);
+/* y = x + f(x); x, y HR volumes [s][n][m] (may not alias). */
+int sr3d_cnn_forward(sr3d_dims dims, const float *params, const float *x, float *y,
+                     void *ws, size_t ws_bytes, hipStream_t stream);
+/* loss (device float) = mean((x + f(x) - target)^2) and grad (device,
+ * sr3d_cnn_param_count() floats) = its gradient with respect to params. */
+int sr3d_cnn_grad(sr3d_dims dims, const float *params, const float *x, const float *target,
+                  float *grad, float *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+/* One Adam step (bias-corrected, step counted from 1) on all parameters. */
+int sr3d_cnn_adam(float *params, const float *grad, float *m, float *v, int step, float lr,
+                  float beta1, float beta2, float eps, hipStream_t stream);
+/* Single convolution layers (the network's building blocks). Forward:
+ * cin = 1, cout = 32 reads the FP32 volume x (rounded to bfloat16);
+ * cin = cout = 32 reads in_bf16 [voxel][32]. weight [27][cout][cin] FP32
+ * (rounded to bfloat16), bias [cout]; output after ReLU as bfloat16
+ * [voxel][32] and, if out_f32 is non-NULL, before rounding in FP32.
+ * Backward (cin = cout = 32): gweight [27][32][32] then gbias [32] (FP32)
+ * from the layer input act_in_bf16 and the output gradient gout_bf16; if
+ * gin_bf16 is non-NULL also the input gradient, zeroed where mask_bf16 <= 0. */
+size_t sr3d_conv3d_workspace_size(sr3d_dims dims);
+int sr3d_conv3d_forward(sr3d_dims dims, int cin, int cout, const void *in_bf16, const float *x,
+                        const float *weight, const float *bias, void *out_bf16, float *out_f32,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+int sr3d_conv3d_backward(sr3d_dims dims, const void *act_in_bf16, const void *gout_bf16,
+                         const float *weight, const void *mask_bf16, void *gin_bf16,
+                         float *gin_f32, float *gweight, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* FFT autotuner. Every axis kernel (R2C/C2R along m, forward/inverse along n
  * and s) comes in tile variants of 2048, 4096 and 8192 complex elements per
  * workgroup. sr3d_autotune times each variant for every HR and LR transform

@@ -861,6 +861,109 @@ const char *sr3d_status_string(int s) {
 
 const char *sr3d_last_error(void) { return g_err.c_str(); }
 
+static int check_cnn_dims(sr3d_dims d, long *NV) {
+  if (d.m < 1 || d.n < 1 || d.s < 1) return fail(SR3D_ERR_INVALID_ARG, "dimensions must be >= 1");
+  const long nv = (long)d.m * d.n * d.s;
+  if (nv >= (1L << 31)) return fail(SR3D_ERR_UNSUPPORTED_SIZE, "volume too large");
+  *NV = nv;
+  return SR3D_OK;
+}
+
+size_t sr3d_cnn_param_count(void) { return (size_t)cnn_param_count(); }
+
+int sr3d_cnn_init(float *params, unsigned long long seed, hipStream_t st) {
+  if (!params) return fail(SR3D_ERR_INVALID_ARG, "params is NULL");
+  SR3D_TRY(cnn_init(params, seed, st), "cnn init");
+  return SR3D_OK;
+}
+
+size_t sr3d_cnn_workspace_size(sr3d_dims d, int training) {
+  long nv;
+  if (check_cnn_dims(d, &nv)) return 0;
+  return cnn_layout(nv, training != 0, nullptr).bytes;
+}
+
+int sr3d_cnn_forward(sr3d_dims d, const float *params, const float *x, float *y, void *ws,
+                     size_t ws_bytes, hipStream_t st) {
+  long nv;
+  int rc = check_cnn_dims(d, &nv);
+  if (rc) return rc;
+  if (!params || !x || !y) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  if (x == y) return fail(SR3D_ERR_INVALID_ARG, "y aliases x");
+  const CnnWs L0 = cnn_layout(nv, false, nullptr);
+  if (!ws || ws_bytes < L0.bytes) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  const CnnWs L = cnn_layout(nv, false, reinterpret_cast<char *>(ws));
+  SR3D_TRY(cnn_forward(d.s, d.n, d.m, params, x, y, L, false, nullptr, nullptr, nullptr, st),
+           "cnn forward");
+  return SR3D_OK;
+}
+
+int sr3d_cnn_grad(sr3d_dims d, const float *params, const float *x, const float *target,
+                  float *grad, float *loss, void *ws, size_t ws_bytes, hipStream_t st) {
+  long nv;
+  int rc = check_cnn_dims(d, &nv);
+  if (rc) return rc;
+  if (!params || !x || !target || !grad || !loss) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  const CnnWs L0 = cnn_layout(nv, true, nullptr);
+  if (!ws || ws_bytes < L0.bytes) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  const CnnWs L = cnn_layout(nv, true, reinterpret_cast<char *>(ws));
+  SR3D_TRY(cnn_grad(d.s, d.n, d.m, params, x, target, grad, loss, L, st), "cnn grad");
+  return SR3D_OK;
+}
+
+int sr3d_cnn_adam(float *params, const float *grad, float *m, float *v, int step, float lr,
+                  float beta1, float beta2, float eps, hipStream_t st) {
+  if (!params || !grad || !m || !v) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(SR3D_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  SR3D_TRY(cnn_adam(params, grad, m, v, step, lr, beta1, beta2, eps, st), "adam");
+  return SR3D_OK;
+}
+
+size_t sr3d_conv3d_workspace_size(sr3d_dims d) {
+  long nv;
+  if (check_cnn_dims(d, &nv)) return 0;
+  return 256 + ((27 * 32 * 32 * sizeof(uint16_t) + 255) & ~(size_t)255) + conv_layer_partial_bytes(nv);
+}
+
+int sr3d_conv3d_forward(sr3d_dims d, int cin, int cout, const void *in_bf16, const float *x,
+                        const float *weight, const float *bias, void *out_bf16, float *out_f32,
+                        void *ws, size_t ws_bytes, hipStream_t st) {
+  long nv;
+  int rc = check_cnn_dims(d, &nv);
+  if (rc) return rc;
+  if (!((cin == 1 && cout == 32 && x) || (cin == 32 && cout == 32 && in_bf16)))
+    return fail(SR3D_ERR_INVALID_ARG, "supported layers: 1->32 (x) and 32->32 (in_bf16)");
+  if (!weight || !bias || !out_bf16) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  if (!ws || ws_bytes < sr3d_conv3d_workspace_size(d)) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  uint16_t *wbf = reinterpret_cast<uint16_t *>(ws);
+  SR3D_TRY(to_bf16(weight, wbf, 27L * cin * cout, st), "weights to bf16");
+  SR3D_TRY(conv_layer_forward(d.s, d.n, d.m, cin, cout, in_bf16, x, wbf, bias, out_bf16, out_f32, st),
+           "conv forward");
+  return SR3D_OK;
+}
+
+int sr3d_conv3d_backward(sr3d_dims d, const void *act_in_bf16, const void *gout_bf16,
+                         const float *weight, const void *mask_bf16, void *gin_bf16,
+                         float *gin_f32, float *gweight, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+  long nv;
+  int rc = check_cnn_dims(d, &nv);
+  if (rc) return rc;
+  if (!act_in_bf16 || !gout_bf16 || !weight || !gweight) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  if (gin_bf16 && !mask_bf16) return fail(SR3D_ERR_INVALID_ARG, "input gradient needs a mask");
+  if (!ws || ws_bytes < sr3d_conv3d_workspace_size(d)) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  uint16_t *wbf = reinterpret_cast<uint16_t *>(ws);
+  float *partial = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) +
+                                             ((27 * 32 * 32 * sizeof(uint16_t) + 255) & ~(size_t)255));
+  SR3D_TRY(to_bf16(weight, wbf, 27L * 32 * 32, st), "weights to bf16");
+  SR3D_TRY(conv_layer_backward(d.s, d.n, d.m, act_in_bf16, gout_bf16, wbf, mask_bf16, gin_bf16,
+                               gin_f32, gweight, partial, st),
+           "conv backward");
+  return SR3D_OK;
+}
+
 int sr3d_autotune(const sr3d_problem *p, int count, int force, hipStream_t st) {
   if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
   Geometry g;

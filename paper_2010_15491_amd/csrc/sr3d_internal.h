@@ -198,4 +198,32 @@ hipError_t spectrum_mul(float2 *W, const float2 *Lam, size_t n, float scale, hip
 hipError_t decimate(const float *x, float *y, int S, int N, int M, int dr, int dc, int ds,
                     hipStream_t st);
 
+// Warm-start CNN (cnn.hip).
+struct CnnWs {
+  uint16_t *wbf;     // bf16 copy of the parameters
+  uint16_t *act[5];  // hidden activations [voxel][32] (inference uses act[0..1])
+  uint16_t *gz[2];   // gradients at layer outputs
+  float *gout, *y, *partial, *lpart;
+  size_t bytes;
+};
+long cnn_param_count();
+long cnn_w_offset(int layer);
+CnnWs cnn_layout(long NV, bool training, char *base);
+hipError_t cnn_init(float *params, uint64_t seed, hipStream_t st);
+hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int step, float lr, float b1,
+                    float b2, float eps, hipStream_t st);
+hipError_t cnn_forward(int S, int N, int M, const float *params, const float *x, float *y,
+                       const CnnWs &L, bool training, const float *target, float *gout,
+                       float *lpart, hipStream_t st);
+hipError_t cnn_grad(int S, int N, int M, const float *params, const float *x, const float *target,
+                    float *grad, float *loss, const CnnWs &L, hipStream_t st);
+hipError_t conv_layer_forward(int S, int N, int M, int cin, int cout, const void *in,
+                              const float *x, const uint16_t *wbf, const float *bias, void *out_bf16,
+                              float *out_f32, hipStream_t st);
+hipError_t conv_layer_backward(int S, int N, int M, const void *act_in, const void *gz,
+                               const uint16_t *wbf, const void *mask, void *gin_bf16,
+                               float *gin_f32, float *gw, float *partial, hipStream_t st);
+size_t conv_layer_partial_bytes(long NV);
+hipError_t to_bf16(const float *p, uint16_t *q, long n, hipStream_t st);
+
 }  // namespace sr3d

@@ -34,7 +34,10 @@ def CHECK_INTERVAL(k):
 OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
 
 EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
-           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_autotune",
+           "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_cnn_param_count",
+           "sr3d_cnn_init", "sr3d_cnn_workspace_size", "sr3d_cnn_forward", "sr3d_cnn_grad",
+           "sr3d_cnn_adam", "sr3d_conv3d_workspace_size", "sr3d_conv3d_forward",
+           "sr3d_conv3d_backward", "sr3d_autotune",
            "sr3d_tune_save", "sr3d_tune_load", "sr3d_profile_read",
            "sr3d_profile_reset", "sr3d_status_string", "sr3d_last_error", "sr3d_shutdown"]
 
@@ -95,6 +98,24 @@ def load():
         lib.sr3d_status_string.restype = ctypes.c_char_p
         lib.sr3d_last_error.argtypes = []
         lib.sr3d_last_error.restype = ctypes.c_char_p
+        lib.sr3d_cnn_param_count.argtypes = []
+        lib.sr3d_cnn_param_count.restype = sz
+        lib.sr3d_cnn_init.argtypes = [vp, ctypes.c_ulonglong, vp]
+        lib.sr3d_cnn_init.restype = ci
+        lib.sr3d_cnn_workspace_size.argtypes = [Dims, ci]
+        lib.sr3d_cnn_workspace_size.restype = sz
+        lib.sr3d_cnn_forward.argtypes = [Dims, vp, vp, vp, vp, sz, vp]
+        lib.sr3d_cnn_forward.restype = ci
+        lib.sr3d_cnn_grad.argtypes = [Dims, vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.sr3d_cnn_grad.restype = ci
+        lib.sr3d_cnn_adam.argtypes = [vp, vp, vp, vp, ci, cf, cf, cf, cf, vp]
+        lib.sr3d_cnn_adam.restype = ci
+        lib.sr3d_conv3d_workspace_size.argtypes = [Dims]
+        lib.sr3d_conv3d_workspace_size.restype = sz
+        lib.sr3d_conv3d_forward.argtypes = [Dims, ci, ci, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.sr3d_conv3d_forward.restype = ci
+        lib.sr3d_conv3d_backward.argtypes = [Dims, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        lib.sr3d_conv3d_backward.restype = ci
         lib.sr3d_autotune.argtypes = [ctypes.POINTER(Problem), ci, ci, vp]
         lib.sr3d_autotune.restype = ci
         lib.sr3d_tune_save.argtypes = [ctypes.c_char_p]
@@ -285,6 +306,123 @@ def irfft3d(spec, shape, stream=None):
     out = torch.empty(tuple(shape), dtype=torch.float32, device=spec.device)
     _check(load().sr3d_irfft3d(dims_of(shape), _ptr(sp), _ptr(out), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start
+# ---------------------------------------------------------------------------
+
+def cnn_param_count():
+    return int(load().sr3d_cnn_param_count())
+
+
+def cnn_init(seed, device="cuda", stream=None):
+    import torch
+    p = torch.empty(cnn_param_count(), dtype=torch.float32, device=device)
+    _check(load().sr3d_cnn_init(_ptr(p), int(seed), _stream(stream)))
+    return p
+
+
+class CnnWorkspace:
+    """Reusable workspaces for one volume size."""
+
+    def __init__(self, shape, device="cuda"):
+        import torch
+        self.shape = tuple(shape)
+        d = dims_of(shape)
+        self.fwd = torch.empty(int(load().sr3d_cnn_workspace_size(d, 0)), dtype=torch.uint8,
+                               device=device)
+        self.train = None
+        self.device = device
+
+    def training(self):
+        import torch
+        if self.train is None:
+            self.train = torch.empty(int(load().sr3d_cnn_workspace_size(dims_of(self.shape), 1)),
+                                     dtype=torch.uint8, device=self.device)
+        return self.train
+
+
+def cnn_forward(params, x, out=None, ws=None, stream=None):
+    """x0 = x + f(x)."""
+    import torch
+    _dev_f32(params, "params")
+    _dev_f32(x, "x")
+    ws = ws or CnnWorkspace(x.shape, x.device)
+    y = out if out is not None else torch.empty_like(x)
+    _check(load().sr3d_cnn_forward(dims_of(x.shape), _ptr(params), _ptr(x), _ptr(y), _ptr(ws.fwd),
+                                   ws.fwd.numel(), _stream(stream)))
+    return y
+
+
+def cnn_grad(params, x, target, grad=None, loss=None, ws=None, stream=None):
+    """(loss, grad) of mean((x + f(x) - target)^2); loss is a 1-element tensor."""
+    import torch
+    _dev_f32(params, "params")
+    _dev_f32(x, "x")
+    _dev_f32(target, "target")
+    ws = ws or CnnWorkspace(x.shape, x.device)
+    g = grad if grad is not None else torch.empty_like(params)
+    ls = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+    t = ws.training()
+    _check(load().sr3d_cnn_grad(dims_of(x.shape), _ptr(params), _ptr(x), _ptr(target), _ptr(g),
+                                _ptr(ls), _ptr(t), t.numel(), _stream(stream)))
+    return ls, g
+
+
+def cnn_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().sr3d_cnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def _dev_bf16(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.bfloat16:
+        raise TypeError(f"{name} must be a CUDA bfloat16 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def conv3d_forward(shape, weight, bias, x=None, act=None, stream=None):
+    """One layer: 1->32 from the FP32 volume x, or 32->32 from act (bf16,
+    (s, n, m, 32)). Returns (out bf16 (s, n, m, 32), out FP32 before rounding)."""
+    import torch
+    cin = 1 if act is None else 32
+    if cin == 1:
+        _dev_f32(x, "x")
+    else:
+        _dev_bf16(act, "act")
+    dev = weight.device
+    out = torch.empty(tuple(shape) + (32,), dtype=torch.bfloat16, device=dev)
+    out32 = torch.empty(tuple(shape) + (32,), dtype=torch.float32, device=dev)
+    d = dims_of(shape)
+    ws = torch.empty(int(load().sr3d_conv3d_workspace_size(d)), dtype=torch.uint8, device=dev)
+    _check(load().sr3d_conv3d_forward(d, cin, 32, _ptr(act), _ptr(x), _ptr(weight), _ptr(bias),
+                                      _ptr(out), _ptr(out32), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+    return out, out32
+
+
+def conv3d_backward(shape, act_in, gout, weight, mask=None, stream=None):
+    """32->32 layer backward: returns (gweight+gbias FP32 (27*32*32+32,),
+    gin bf16 or None, gin FP32 or None)."""
+    import torch
+    _dev_bf16(act_in, "act_in")
+    _dev_bf16(gout, "gout")
+    dev = weight.device
+    gw = torch.empty(27 * 32 * 32 + 32, dtype=torch.float32, device=dev)
+    gin = gin32 = None
+    if mask is not None:
+        _dev_bf16(mask, "mask")
+        gin = torch.empty(tuple(shape) + (32,), dtype=torch.bfloat16, device=dev)
+        gin32 = torch.empty(tuple(shape) + (32,), dtype=torch.float32, device=dev)
+    d = dims_of(shape)
+    ws = torch.empty(int(load().sr3d_conv3d_workspace_size(d)), dtype=torch.uint8, device=dev)
+    _check(load().sr3d_conv3d_backward(d, _ptr(act_in), _ptr(gout), _ptr(weight), _ptr(mask),
+                                       _ptr(gin), _ptr(gin32), _ptr(gw), _ptr(ws), ws.numel(),
+                                       _stream(stream)))
+    return gw, gin, gin32
 
 
 def autotune(shapes_rates, force=False, stream=None):
