@@ -122,9 +122,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
-    ap.add_argument("--workload", default="tv256", choices=["tv256", "batch64"],
+    ap.add_argument("--workload", default="tv256", choices=["tv256", "batch64", "warm256"],
                     help="tv256: the headline single-volume solve; batch64: 64 uneven volumes, "
-                         "sequential single solves vs one batched solve")
+                         "sequential single solves vs one batched solve; warm256: train the "
+                         "warm-start CNN on 64^3 pairs, then plain vs warm-started solves at 256^3")
+    ap.add_argument("--pairs", type=int, default=2000, help="warm256: training pairs")
+    ap.add_argument("--train-steps", type=int, default=4000, help="warm256: Adam steps")
+    ap.add_argument("--eval-volumes", type=int, default=4, help="warm256: 256^3 test volumes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -132,6 +136,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         return bench_batch64(args)
+    if args.workload == "warm256":
+        return bench_warm256(args)
 
     import numpy as np
     import torch
@@ -314,6 +320,99 @@ def bench_batch64(args):
                    "same_iters_as_sequential": same_iters, "max_rel_l2_vs_sequential": max_rel},
         "sequential": {"value": nh / (ms_seq / 1e3), "ms_per_step": ms_seq},
         "speedup_vs_sequential": ms_seq / ms_bat,
+    }
+    print(json.dumps(out), flush=True)
+
+
+VARIANTS = ("plain", "tikhonov_x0", "cnn_x0", "tikhonov_x0_dual", "cnn_x0_dual")
+
+
+def bench_warm256(args):
+    """Learned warm start: pairs from 64^3 phantoms (batched plain ADMM), GPU
+    training, then on 256^3 volumes like the headline workload: iterations and
+    wall time to reach the plain run's final residuals from x0 = 0, from the
+    Tikhonov solution, and from the CNN (Tikhonov and inference included)."""
+    import numpy as np
+    import torch
+    from paper_2010_15491_amd import phantom, sr3d, warmstart
+
+    sr3d.load()
+    dev = torch.device("cuda:0")
+    wl = WORKLOAD
+    sr3d.autotune([((64, 64, 64), (2, 2, 2)), (wl["hr"], wl["rate"])])
+    (pairs, pst), t_pairs = warmstart.timed(
+        lambda: warmstart.make_pairs(range(1000, 1000 + args.pairs)))
+    print(f"pairs: {len(pairs)} in {t_pairs:.1f} s", file=sys.stderr, flush=True)
+    (params, losses, _), t_train = warmstart.timed(
+        lambda: warmstart.train(pairs, args.train_steps))
+    print(f"trained {args.train_steps} steps in {t_train:.1f} s, loss {losses[0]:.3e} -> "
+          f"{np.mean(losses[-50:]):.3e}", file=sys.stderr, flush=True)
+    del pairs
+    torch.cuda.empty_cache()
+    hr, rate = wl["hr"], wl["rate"]
+    nh = hr[0] * hr[1] * hr[2]
+    cws = sr3d.CnnWorkspace(hr)
+    x = torch.empty(hr, dtype=torch.float32, device=dev)
+    ws = torch.empty(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [sr3d._problem(hr, rate, torch.ones(
+        7, 7, 7, device=dev))]), dtype=torch.uint8, device=dev)
+    runs = []
+    for k in range(args.eval_volumes):
+        p = phantom.make_problem(hr, rate, wl["sigma"], wl["noise"], 5000 + k, texture=True)
+        psf = torch.from_numpy(p["psf"].astype("float32")).to(dev)
+        y = sr3d.degrade(torch.from_numpy(p["x_true"].astype("float32")).to(dev), psf, rate)
+        y += torch.from_numpy(p["noise"].astype("float32")).to(dev)
+
+        def admm(x0, tol, told, dual=False):
+            fl = sr3d.FP64_REDUCE | (sr3d.WARM_DUAL if dual else 0)
+            return sr3d.tv_admm(y, psf, rate, wl["lam"], wl["mu"], wl["max_iter"], tol=tol,
+                                tol_dual=told, x0=x0, out=x, workspace=ws, flags=fl)
+
+        if k == 0:  # warm-up of every kernel involved
+            admm(None, wl["tol"], 0.0)
+            warmstart.warm_start(params, y, psf, rate, ws=cws)
+        (_, st0), t0 = warmstart.timed(lambda: admm(None, wl["tol"], 0.0))
+        tp, td = max(wl["tol"], st0.primal_rel), max(wl["tol"], st0.dual_rel)
+        (_, stp), tpl = warmstart.timed(lambda: admm(None, tp, td))
+        (_, stt), tt = warmstart.timed(
+            lambda: admm(sr3d.tikhonov(y, psf, rate, 1e-3), tp, td))
+        xt = sr3d.tikhonov(y, psf, rate, 1e-3)
+        _, t_inf = warmstart.timed(lambda: sr3d.cnn_forward(params, xt, ws=cws))
+        (_, stc), tc = warmstart.timed(
+            lambda: admm(warmstart.warm_start(params, y, psf, rate, ws=cws), tp, td))
+        (_, sttd), ttd = warmstart.timed(
+            lambda: admm(sr3d.tikhonov(y, psf, rate, 1e-3), tp, td, dual=True))
+        (_, stcd), tcd = warmstart.timed(
+            lambda: admm(warmstart.warm_start(params, y, psf, rate, ws=cws), tp, td, dual=True))
+        runs.append({"seed": 5000 + k, "plain_cap_run": {"iters": st0.iters, "s": t0,
+                                                         "primal": st0.primal_rel,
+                                                         "dual": st0.dual_rel},
+                     "target": [tp, td],
+                     "plain": {"iters": stp.iters, "reached": stp.converged, "s": tpl},
+                     "tikhonov_x0": {"iters": stt.iters, "reached": stt.converged, "s": tt},
+                     "cnn_x0": {"iters": stc.iters, "reached": stc.converged, "s": tc,
+                                "inference_s": t_inf},
+                     "tikhonov_x0_dual": {"iters": sttd.iters, "reached": sttd.converged, "s": ttd},
+                     "cnn_x0_dual": {"iters": stcd.iters, "reached": stcd.converged, "s": tcd}})
+        print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    flops = 2.0 * 27 * (32 + 4 * 32 * 32 + 32) * nh
+    mean = lambda key, f: float(np.mean([f(r[key]) for r in runs]))
+    out = {
+        "metric": "warm start: wall time to the plain solve's final residuals, 256^3 TV-ADMM",
+        "value": mean("plain", lambda r: r["s"]) / mean("cnn_x0_dual", lambda r: r["s"]),
+        "unit": "speedup (plain / CNN warm start with dual init, inference included)",
+        "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32 solver, bf16 CNN", "data": "synthetic",
+        "config": {"workload": "warm256", "train_pairs": args.pairs, "train_steps": args.train_steps,
+                   "pair_generation_s": t_pairs, "train_s": t_train,
+                   "train_loss_first": losses[0], "train_loss_last50": float(np.mean(losses[-50:])),
+                   "pair_admm_converged": int(sum(s.converged for s in pst))},
+        "cnn_inference_256": {"s": float(np.mean([r["cnn_x0"]["inference_s"] for r in runs])),
+                              "tflops": flops / float(np.mean([r["cnn_x0"]["inference_s"]
+                                                               for r in runs])) / 1e12},
+        "mean_iters": {k: mean(k, lambda r: r["iters"]) for k in VARIANTS},
+        "mean_s": {k: mean(k, lambda r: r["s"]) for k in VARIANTS},
+        "reached": {k: int(sum(r[k]["reached"] for r in runs)) for k in VARIANTS},
+        "runs": runs,
     }
     print(json.dumps(out), flush=True)
 

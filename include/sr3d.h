@@ -76,6 +76,7 @@ typedef struct {
   const float *x0;     /* device HR initial guess, or NULL for x0 = 0 */
   float *x;            /* device HR output [s_h][n_h][m_h] */
   float *state;        /* optional device buffer of 3*N_h floats, or NULL (see below) */
+  float tol_dual;      /* tolerance of the relative dual residual; <= 0 means tol */
 } sr3d_problem;
 
 /* sr3d_problem.state: the ADMM state (u, d) is kept as nu = L x + d_prev
@@ -91,6 +92,9 @@ typedef struct {
 #define SR3D_USE_GRAPH   0x4   /* replay captured iterations as a HIP graph */
 #define SR3D_PROFILE     0x8   /* time every kernel launch with HIP events on the caller's
                                   stream; totals per stage via sr3d_profile_read (no graph) */
+#define SR3D_WARM_DUAL   0x10  /* with x0: also start the scaled dual d from the minimum-norm
+                                  solution of the x-update's stationarity at x0,
+                                  mu L^T d = H^T D^T (y - D H x0) (nu0 = L(x0 + phi)) */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */
@@ -119,7 +123,8 @@ int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf
  * x-update 5a through eq. (12) in the Fourier domain (the zero-frequency alias
  * group, where Gamma = 1/G is unbounded, by exact elimination), then 5b, 5c.
  * Stops when ||Lx-u'|| <= tol max(||Lx||,||u'||) and
- * mu||L^T(u'-u)|| <= tol mu||L^T d'||, or after max_iter iterations.
+ * mu||L^T(u'-u)|| <= tol_dual mu||L^T d'|| (tol_dual = tol unless set), or
+ * after max_iter iterations.
  * `stats` (host) may be NULL. */
 int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats,
                  void *ws, size_t ws_bytes, hipStream_t stream);

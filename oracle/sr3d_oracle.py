@@ -41,7 +41,7 @@ __all__ = [
     "WORKERS", "hr_shape_of", "lr_shape_of", "psf_to_otf", "blur", "blur_adjoint",
     "decimate", "zero_fill", "degrade", "fold", "unfold", "diff_symbol_sq",
     "grad", "grad_adjoint", "shrink", "tikhonov", "tikhonov_objective",
-    "x_update", "AdmmResult", "admm_tv", "tv_objective", "data_term", "psnr",
+    "x_update", "AdmmResult", "admm_tv", "min_norm_dual", "tv_objective", "data_term", "psnr",
     "rel_l2",
 ]
 
@@ -311,8 +311,21 @@ def _rel(num, den):
     return num / den if den > 0 else float("inf")
 
 
+def min_norm_dual(x0, y, psf, rate, mu):
+    """Dual warm start (an extension, not in the paper): the minimum-norm d with
+    mu L^T d = H^T D^T (y - D H x0) - (its mean), i.e. d = L phi,
+    phi = (L^T L)^+ H^T D^T (y - D H x0) / mu (pseudo-inverse: zero mean)."""
+    hr = x0.shape
+    otf = psf_to_otf(psf, hr)
+    r = zero_fill(y - degrade(x0, psf, rate), rate)
+    R = np.conj(otf) * _fftn(r)
+    G = diff_symbol_sq(hr)
+    Phi = np.where(G > 0, R / (mu * np.where(G > 0, G, 1.0)), 0.0)
+    return grad(np.real(_ifftn(Phi)))
+
+
 def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
-            callback=None):
+            callback=None, warm_dual=False, tol_dual=None):
     """3D-FSR-l2-TV (Algorithm 1).
 
     Inputs y, H (through ``psf``), lam, r = prod(rate), mu.
@@ -336,6 +349,8 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
 
     x = np.zeros(hr) if x0 is None else np.asarray(x0, np.float64).copy()
     nu = grad(x)
+    if x0 is not None and warm_dual:
+        nu = nu + min_norm_dual(x, y, psf, rate, mu)
     u = shrink(nu, thr)
     d = nu - u
 
@@ -363,7 +378,7 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
         if callback is not None:
             callback(it, x, u, d, u_new, d_new)
         u, d = u_new, d_new
-        if tol > 0 and prel <= tol and drel <= tol:
+        if tol > 0 and prel <= tol and drel <= (tol if not tol_dual else tol_dual):
             converged = True
             break
     return AdmmResult(x=x, u=u, d=d, iters=it, converged=converged,

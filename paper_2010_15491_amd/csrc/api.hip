@@ -258,8 +258,11 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
   if (!(p->lambda_tv > 0.f) || !(p->mu > 0.f) || !isfinite(p->lambda_tv) || !isfinite(p->mu))
     return fail(SR3D_ERR_INVALID_ARG, "lambda_tv and mu must be finite and > 0");
   if (!(p->tol >= 0.f) || !isfinite(p->tol)) return fail(SR3D_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (!isfinite(p->tol_dual)) return fail(SR3D_ERR_INVALID_ARG, "tol_dual must be finite");
   if (p->max_iter < 1) return fail(SR3D_ERR_INVALID_ARG, "max_iter must be >= 1");
   if ((flags & SR3D_RESUME) && !p->state) return fail(SR3D_ERR_INVALID_ARG, "SR3D_RESUME needs problem.state");
+  if ((flags & SR3D_WARM_DUAL) && p->x0 && p->x0 == p->x)
+    return fail(SR3D_ERR_INVALID_ARG, "SR3D_WARM_DUAL needs x0 distinct from x");
   if (p->x == p->y || p->x == p->psf) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
   return SR3D_OK;
 }
@@ -268,15 +271,31 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
 hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu0, int flags,
                     hipStream_t st) {
   hipError_t e;
-  if ((e = ctrl_init(L.ctrl, p->max_iter, p->tol, p->mu, p->lambda_tv, 1.0 / (double)g.NL, st))) return e;
+  if ((e = ctrl_init(L.ctrl, p->max_iter, p->tol, p->tol_dual, p->mu, p->lambda_tv,
+                     1.0 / (double)g.NL, st)))
+    return e;
   if ((e = pad_psf(p->psf, p->psf_dims.s, p->psf_dims.n, p->psf_dims.m, L.theta, g.S, g.N, g.M, st))) return e;
   if ((e = fft3d_forward(L.theta, L.lam, g.S, g.N, g.M, nullptr, st))) return e;
   if ((e = fft3d_forward(p->y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st))) return e;
   if ((e = diff_tables(L.g, g.S, g.N, g.M, st))) return e;
   const float thr = p->lambda_tv / p->mu;
   if (flags & SR3D_RESUME) return theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st);
+  const float *xinit = p->x0;
+  if (p->x0 && (flags & SR3D_WARM_DUAL)) {
+    // nu0 = L (x0 + phi): u0 = shrink(nu0), d0 = nu0 - u0 start from the
+    // minimum-norm dual that makes x0 stationary for the x-update.
+    if ((e = fft3d_forward(p->x0, L.w, g.S, g.N, g.M, nullptr, st))) return e;
+    FoldArgs fa = make_fold(g);
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+    fa.coefA = p->mu;
+    if ((e = dual_init_spectrum(fa, st))) return e;
+    if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, nullptr, st))) return e;
+    if ((e = add_to(p->x, p->x0, (size_t)g.NH, st))) return e;
+    xinit = p->x;
+  }
   AdmmStencilArgs sa{};
-  sa.x = p->x0; sa.nu_in = nullptr; sa.nu_out = nu0; sa.theta = L.theta;
+  sa.x = xinit; sa.nu_in = nullptr; sa.nu_out = nu0; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = thr; sa.part = nullptr; sa.done = nullptr;
   return admm_stencil(sa, false, false, st);
 }

@@ -240,6 +240,93 @@ static hipError_t launch_fold(const FoldArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Dual warm start. For x0 with spectrum W, the minimum-norm d solving the
+// stationarity of the x-update, mu L^T d = H^T D^T (y - D H x0), is d = L phi
+// with phi = (L^T L)^+ H^T D^T (y - D H x0) / mu. In the Fourier domain
+//   Phi_k = conj(L_k) Z_j / (mu G_k),  Z_j = Y_j - (1/d) sum_a L_a W_a,
+// with Phi_0 = 0. Output scaled by `scale` for the inverse FFT.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_dual_init(FoldArgs a) {
+  const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
+  const long g = (long)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= ngroups) return;
+  const int jm = (int)(g % a.ml_eff);
+  const long r1 = g / a.ml_eff;
+  const int jn = (int)(r1 % a.Nl);
+  const int js = (int)(r1 / a.Nl);
+  float2 Yj;
+  if (jm < a.Mlh) {
+    Yj = a.Yh[((long)js * a.Nl + jn) * a.Mlh + jm];
+  } else {
+    const int ms = (a.Sl - js) % a.Sl, mn = (a.Nl - jn) % a.Nl;
+    Yj = c_conj(a.Yh[((long)ms * a.Nl + mn) * a.Mlh + (a.Ml - jm)]);
+  }
+  float2 lam[D];
+  float A[D];
+  long idx[D];
+  bool own[D];
+  float2 z = Yj;
+  int ia = 0, ib = 0, ic = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const int km = jm + ia * a.Ml, kn = jn + ib * a.Nl, ks = js + ic * a.Sl;
+    const bool direct = km < a.Mh;
+    long id;
+    if (direct) {
+      id = ((long)ks * a.N + kn) * a.Mh + km;
+    } else {
+      const int ms = (a.S - ks) % a.S, mn = (a.N - kn) % a.N;
+      id = ((long)ms * a.N + mn) * a.Mh + (a.M - km);
+    }
+    float2 l = a.Lam[id], w = a.W[id];
+    if (!direct) {
+      l.y = -l.y;
+      w.y = -w.y;
+    }
+    const float2 lw = c_mul(l, w);
+    z.x -= lw.x / (float)D;
+    z.y -= lw.y / (float)D;
+    lam[q] = l;
+    A[q] = a.coefA * (a.gs[ks] + a.gn[kn] + a.gm[km]);
+    idx[q] = id;
+    own[q] = direct;
+    if (++ia == a.dr) {
+      ia = 0;
+      if (++ib == a.dc) {
+        ib = 0;
+        ++ic;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    if (!own[q]) continue;
+    float2 v = make_float2(0.f, 0.f);
+    if (A[q] > 0.f) {
+      const float2 t = c_mul(c_conj(lam[q]), z);
+      v = make_float2(t.x / A[q] * a.scale, t.y / A[q] * a.scale);
+    }
+    a.X[idx[q]] = v;
+  }
+}
+
+hipError_t dual_init_spectrum(const FoldArgs &a, hipStream_t st) {
+  const int D = a.dr * a.dc * a.ds;
+  dim3 g((unsigned)fold_blocks(a)), b(kThreads);
+  switch (D) {
+#define SR3D_D(DD)                                                 \
+  case DD:                                                         \
+    hipLaunchKernelGGL((k_dual_init<DD>), g, b, 0, st, a);         \
+    break;
+    SR3D_D(1) SR3D_D(2) SR3D_D(3) SR3D_D(4) SR3D_D(6) SR3D_D(8) SR3D_D(9) SR3D_D(12)
+    SR3D_D(16) SR3D_D(18) SR3D_D(24) SR3D_D(27) SR3D_D(32) SR3D_D(36) SR3D_D(48) SR3D_D(64)
+#undef SR3D_D
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename Acc>
 static hipError_t launch_fold_batch(int D, const FoldArgs *descs, const int2 *items, int nitems,
                                     hipStream_t st) {

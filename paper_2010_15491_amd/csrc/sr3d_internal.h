@@ -20,7 +20,7 @@ struct Ctrl {
   int status;     // 0 or a negative sr3d_status found on the device
   int max_iter;
   int counted;    // batch: this volume's stop has been counted
-  float tol, mu, lam, pad1;
+  float tol, mu, lam, tol_dual;
   double primal_rel, dual_rel, objective;
   double inv_nl;  // 1 / N_l (LR Parseval factor of the data term)
 };
@@ -144,6 +144,7 @@ struct FoldArgs {
 };
 int fold_blocks(const FoldArgs &a);
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
+hipError_t dual_init_spectrum(const FoldArgs &a, hipStream_t st);
 hipError_t fold_solve_batch(int D, const FoldArgs *descs, const int2 *items, int nitems, bool fp64,
                             hipStream_t st);
 
@@ -191,9 +192,10 @@ hipError_t reduce_and_test_batch(const ReduceDesc *descs, int nvol, int *active,
 hipError_t pad_psf(const float *psf, int Ks, int Kn, int Km, float *out, int S, int N, int M,
                    hipStream_t st);
 hipError_t diff_tables(float *g, int S, int N, int M, hipStream_t st);  // g = [gm | gn | gs]
-hipError_t ctrl_init(Ctrl *c, int max_iter, float tol, float mu, float lam, double inv_nl,
-                     hipStream_t st);
+hipError_t ctrl_init(Ctrl *c, int max_iter, float tol, float tol_dual, float mu, float lam,
+                     double inv_nl, hipStream_t st);
 hipError_t fill_zero(float *p, size_t n, hipStream_t st);
+hipError_t add_to(float *y, const float *x, size_t n, hipStream_t st);
 hipError_t spectrum_mul(float2 *W, const float2 *Lam, size_t n, float scale, hipStream_t st);
 hipError_t decimate(const float *x, float *y, int S, int N, int M, int dr, int dc, int ds,
                     hipStream_t st);

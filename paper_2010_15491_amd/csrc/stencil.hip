@@ -441,7 +441,7 @@ __device__ __forceinline__ void reduce_body(Ctrl *c, const Acc *ps, int nbs, con
   }
   bool finite = true;
   for (int k = 0; k < 7; ++k) finite = finite && isfinite(q[k]);
-  const Acc mu = (Acc)c->mu, tol = (Acc)c->tol;
+  const Acc mu = (Acc)c->mu, tol = (Acc)c->tol, tol_d = (Acc)c->tol_dual;
   const Acc r = sqrt(q[0]);
   const Acc pden = fmax(sqrt(q[1]), sqrt(q[2]));
   const Acc s = mu * sqrt(q[4]);
@@ -458,7 +458,7 @@ __device__ __forceinline__ void reduce_body(Ctrl *c, const Acc *ps, int nbs, con
     c->done = 1;
     return;
   }
-  if (tol > 0 && prel <= tol && drel <= tol) {
+  if (tol > 0 && prel <= tol && drel <= tol_d) {
     c->converged = 1;
     c->done = 1;
   }
@@ -560,7 +560,8 @@ hipError_t diff_tables(float *g, int S, int N, int M, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void k_ctrl_init(Ctrl *c, int max_iter, float tol, float mu, float lam, double inv_nl) {
+__global__ void k_ctrl_init(Ctrl *c, int max_iter, float tol, float tol_dual, float mu, float lam,
+                            double inv_nl) {
   if (threadIdx.x != 0) return;
   c->done = 0;
   c->iter = 0;
@@ -571,16 +572,17 @@ __global__ void k_ctrl_init(Ctrl *c, int max_iter, float tol, float mu, float la
   c->tol = tol;
   c->mu = mu;
   c->lam = lam;
-  c->pad1 = 0.f;
+  c->tol_dual = tol_dual > 0.f ? tol_dual : tol;
   c->primal_rel = INFINITY;
   c->dual_rel = INFINITY;
   c->objective = 0.0;
   c->inv_nl = inv_nl;
 }
 
-hipError_t ctrl_init(Ctrl *c, int max_iter, float tol, float mu, float lam, double inv_nl,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, tol, mu, lam, inv_nl);
+hipError_t ctrl_init(Ctrl *c, int max_iter, float tol, float tol_dual, float mu, float lam,
+                     double inv_nl, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, c, max_iter, tol, tol_dual, mu, lam,
+                     inv_nl);
   return hipGetLastError();
 }
 
@@ -592,6 +594,16 @@ __global__ void k_fill_zero(float *p, long n) {
 hipError_t fill_zero(float *p, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, (long)n);
+  return hipGetLastError();
+}
+
+__global__ void k_add_to(float *y, const float *x, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+hipError_t add_to(float *y, const float *x, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_to, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, x, (long)n);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ FP64_REDUCE = 0x1
 RESUME = 0x2
 USE_GRAPH = 0x4
 PROFILE = 0x8
+WARM_DUAL = 0x10
 
 
 def CHECK_INTERVAL(k):
@@ -60,7 +61,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("hr", Dims), ("rate", Rate), ("y", ctypes.c_void_p), ("psf", ctypes.c_void_p),
                 ("psf_dims", Dims), ("lambda_tv", ctypes.c_float), ("mu", ctypes.c_float),
                 ("tol", ctypes.c_float), ("max_iter", ctypes.c_int), ("x0", ctypes.c_void_p),
-                ("x", ctypes.c_void_p), ("state", ctypes.c_void_p)]
+                ("x", ctypes.c_void_p), ("state", ctypes.c_void_p), ("tol_dual", ctypes.c_float)]
 
 
 class Sr3dError(RuntimeError):
@@ -180,9 +181,10 @@ def _workspace(nbytes, device):
 
 
 def _problem(hr_shape, rate, psf, lam=1.0, mu=1.0, tol=0.0, max_iter=1, y=None, x=None, x0=None,
-             state=None):
+             state=None, tol_dual=0.0):
     return Problem(dims_of(hr_shape), rate_of(rate), _ptr(y), _ptr(psf), dims_of(psf.shape),
-                   float(lam), float(mu), float(tol), int(max_iter), _ptr(x0), _ptr(x), _ptr(state))
+                   float(lam), float(mu), float(tol), int(max_iter), _ptr(x0), _ptr(x), _ptr(state),
+                   float(tol_dual))
 
 
 def lr_shape(hr_shape, rate):
@@ -229,7 +231,7 @@ def _stats(s):
 
 
 def tv_admm(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE, state=None,
-            out=None, workspace=None, stream=None):
+            out=None, workspace=None, stream=None, tol_dual=0.0):
     """3D-FSR-l2-TV (Algorithm 1). Returns (x, AdmmStats)."""
     import torch
     _dev_f32(y, "y")
@@ -240,7 +242,8 @@ def tv_admm(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE
         _dev_f32(state, "state")
     hr = hr_shape(tuple(y.shape), rate)
     x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=y.device)
-    p = _problem(hr, rate, psf, lam, mu, tol, max_iter, y=y, x=x, x0=x0, state=state)
+    p = _problem(hr, rate, psf, lam, mu, tol, max_iter, y=y, x=x, x0=x0, state=state,
+                 tol_dual=tol_dual)
     need = workspace_bytes(OP_TV_ADMM, [p])
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, y.device)
     st = Stats()
@@ -263,7 +266,8 @@ def batch(problems, flags=FP64_REDUCE, workspace=None, stream=None):
             x = torch.empty(hr, dtype=torch.float32, device=y.device)
         xs.append(x)
         ps.append(_problem(hr, q["rate"], psf, q["lam"], q["mu"], q.get("tol", 0.0),
-                           q["max_iter"], y=y, x=x, x0=q.get("x0")))
+                           q["max_iter"], y=y, x=x, x0=q.get("x0"),
+                           tol_dual=q.get("tol_dual", 0.0)))
     arr = (Problem * len(ps))(*ps)
     need = int(load().sr3d_workspace_size(OP_BATCH, arr, len(ps)))
     dev = problems[0]["y"].device

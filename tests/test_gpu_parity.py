@@ -197,6 +197,26 @@ def test_tv_admm_warm_start_x0_matches_oracle():
     assert O.rel_l2(host(x), ref.x) < TOL
 
 
+def test_tv_admm_dual_warm_start_matches_oracle():
+    shape, rate = (32, 32, 48), (2, 2, 2)
+    y, psf, x_true = problem(shape, rate, 1.5, 0.02, 12)
+    x0 = f32(O.tikhonov(y, psf, rate, 1e-3))
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10, x0=dev(x0),
+                         flags=sr3d.FP64_REDUCE | sr3d.WARM_DUAL)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 10, x0=x0, warm_dual=True)
+    assert O.rel_l2(host(x), ref.x) < TOL
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=5e-2)
+
+
+def test_tv_admm_separate_dual_tolerance_matches_oracle():
+    shape, rate = (32, 32, 32), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 13)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 150, tol=2e-3, tol_dual=5e-2)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 150, tol=2e-3, tol_dual=5e-2)
+    assert ref.converged and st.converged and abs(st.iters - ref.iters) <= 1
+    assert st.primal_rel <= 2e-3 and st.dual_rel <= 5e-2
+
+
 def test_tv_admm_tolerance_stop_matches_oracle():
     shape, rate = (32, 32, 32), (2, 2, 2)
     y, psf, _ = problem(shape, rate, 1.5, 0.02, 6)

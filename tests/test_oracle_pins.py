@@ -414,3 +414,18 @@ def test_admm_fixed_count_is_deterministic_and_stops():
     b = O.admm_tv(y, psf, rate, 0.02, 0.1, 7)
     assert a.iters == 7 and not a.converged
     assert np.array_equal(a.x, b.x)
+
+
+def test_min_norm_dual_solves_stationarity_with_least_norm():
+    """Dense check at 8x8x8: d = pinv(mu L^T) (H^T D^T (y - D H x0)) projected."""
+    rng = np.random.default_rng(30)
+    shape, rate = (4, 6, 8), (2, 3, 2)
+    psf = rand_psf(rng, (3, 3, 3))
+    mu = 0.07
+    x0 = rng.standard_normal(shape)
+    y = rng.standard_normal(O.lr_shape_of(shape, rate))
+    H, D, L = dense_H(psf, shape), dense_D(shape, rate), dense_L(shape)
+    r = H.T @ D.T @ (y.ravel() - D @ H @ x0.ravel())
+    d_ref = np.linalg.pinv(mu * L.T) @ r
+    d = O.min_norm_dual(x0, y, psf, rate, mu).reshape(-1)
+    assert np.allclose(d, d_ref, atol=1e-10)
