@@ -1,0 +1,77 @@
+"""Precision form: FFTs and pointwise work in FP32, residual/objective
+reductions and the stopping test in FP64 (SR3D_FP64_REDUCE) or FP32, on the
+CBCT-shaped 512 x 512 x 256 volume with d = 2x2x4 and an anisotropic PSF
+sigma = (1.2, 1.2, 2.0), against the FP64 oracle.
+
+By default the GPU and the oracle run 2 iterations (the oracle takes a few
+seconds per iteration at this size). With SR3D_PRECISION_ITERS=100 the study
+runs the full 100 iterations and writes its report to
+gpurun_out/precision_512x512x256.json.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2010_15491_amd import phantom, sr3d
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPE = (256, 512, 512)   # (s, n, m)
+RATE = (2, 2, 4)          # (dr, dc, ds)
+SIGMA = (1.2, 1.2, 2.0)   # (m, n, s)
+LAM, MU = 2e-3, 5e-2
+
+
+def test_precision_study_512x512x256():
+    iters = int(os.environ.get("SR3D_PRECISION_ITERS", "2"))
+    p = phantom.make_problem(SHAPE, RATE, SIGMA, 0.01, 2, texture=True)
+    psf = p["psf"].astype(np.float32).astype(np.float64)
+    assert psf.shape == (9, 7, 7)
+    Pd = torch.from_numpy(psf.astype(np.float32)).cuda()
+    y = sr3d.degrade(torch.from_numpy(p["x_true"].astype(np.float32)).cuda(), Pd, RATE)
+    y += torch.from_numpy(p["noise"].astype(np.float32)).cuda()
+    y_np = y.double().cpu().numpy()
+    res = {}
+    xs = {}
+    for name, flags in (("fp64_reduce", sr3d.FP64_REDUCE), ("fp32_reduce", 0)):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        x, st = sr3d.tv_admm(y, Pd, RATE, LAM, MU, iters, flags=flags)
+        e1.record()
+        torch.cuda.synchronize()
+        xs[name] = x
+        res[name] = {"primal_rel": st.primal_rel, "dual_rel": st.dual_rel,
+                     "objective": st.objective, "iters": st.iters, "ms": e0.elapsed_time(e1)}
+    # the reductions only feed the stopping test: x is the same bits either way
+    assert torch.equal(xs["fp64_reduce"], xs["fp32_reduce"])
+    def progress(it, *_):
+        if it % 10 == 0:
+            print(f"oracle iteration {it}/{iters}", flush=True)
+
+    ref = O.admm_tv(y_np, psf, RATE, LAM, MU, iters, callback=progress)
+    obj_ref = O.tv_objective(ref.x, y_np, psf, RATE, LAM)
+    x = xs["fp64_reduce"].double().cpu().numpy()
+    err = O.rel_l2(x, ref.x)
+    report = {"shape_snm": SHAPE, "rate": RATE, "psf_sigma_mns": SIGMA, "iterations": iters,
+              "x_rel_l2_vs_fp64_oracle": err,
+              "oracle": {"primal_rel": ref.primal_rel, "dual_rel": ref.dual_rel,
+                         "objective": obj_ref}}
+    for name, r in res.items():
+        r["primal_rel_err"] = abs(r["primal_rel"] - ref.primal_rel) / ref.primal_rel
+        r["dual_rel_err"] = abs(r["dual_rel"] - ref.dual_rel) / ref.dual_rel
+        r["objective_err"] = abs(r["objective"] - obj_ref) / abs(obj_ref)
+        report[name] = r
+    print(json.dumps(report))
+    if iters >= 100:
+        os.makedirs("gpurun_out", exist_ok=True)
+        with open(os.path.join("gpurun_out", "precision_512x512x256.json"), "w") as f:
+            json.dump(report, f, indent=1)
+    assert err < 1e-5
+    assert res["fp64_reduce"]["objective_err"] < 1e-6
+    assert res["fp64_reduce"]["primal_rel_err"] < 1e-3
