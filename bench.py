@@ -54,6 +54,9 @@ def alg_bytes_per_voxel(stage, hr, rate):
         "ifft_c2r_m": spec + 4.0,
         # F Theta, Lambda, LR spectrum of y (per HR voxel: 1/d of an LR entry), X
         "fold_solve": 3 * spec + 8.0 * mlh / d,
+        # fused s-FFT + solve + inverse s-FFT: the spectrum read and written
+        # once, Lambda and the LR spectrum of y read once
+        "solve_s": 3 * spec + 8.0 * mlh / d,
         # x and nu_old (3 planes) read; nu_new (3 planes) and Theta written
         "admm_stencil": 4.0 + 12.0 + 12.0 + 4.0,
     }

@@ -95,6 +95,9 @@ typedef struct {
 #define SR3D_WARM_DUAL   0x10  /* with x0: also start the scaled dual d from the minimum-norm
                                   solution of the x-update's stationarity at x0,
                                   mu L^T d = H^T D^T (y - D H x0) (nu0 = L(x0 + phi)) */
+#define SR3D_UNFUSED     0x20  /* run the x-update as separate s-FFT, fold/solve and inverse
+                                  s-FFT kernels even where the fused s-line kernel applies
+                                  (same result up to FP32 rounding; for testing) */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */

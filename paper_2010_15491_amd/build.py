@@ -22,7 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsr3d.so")
 
-SOURCES = ["fft.hip", "fft_m.hip", "fft_strided.hip", "fold.hip", "stencil.hip", "cnn.hip", "api.hip"]
+SOURCES = ["fft.hip", "fft_m.hip", "fft_strided.hip", "fold.hip", "solve_s.hip", "stencil.hip", "cnn.hip",
+           "api.hip"]
 
 ARCH = "gfx950"
 

@@ -31,7 +31,7 @@ double g_prof_ms[kStCount] = {0};
 long g_prof_n[kStCount] = {0};
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
                                      "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
-                                     "reduce_test", "setup"};
+                                     "reduce_test", "solve_s", "setup"};
 }  // namespace
 
 void prof_begin(int stage, hipStream_t st) {
@@ -123,6 +123,7 @@ struct Geometry {
   int S, N, M, Sl, Nl, Ml, Mh, Mlh, D;
   int dr, dc, ds;
   long NH, NL, nspec, nlspec;
+  SolveSPlan sp;  // fused x-update plan (TV)
 };
 
 int check_geometry(sr3d_dims hr, sr3d_rate rate, const sr3d_dims *psf, Geometry *g) {
@@ -153,6 +154,7 @@ int check_geometry(sr3d_dims hr, sr3d_rate rate, const sr3d_dims *psf, Geometry 
     if (psf->m > hr.m || psf->n > hr.n || psf->s > hr.s)
       return fail(SR3D_ERR_PSF_TOO_LARGE, "PSF larger than the HR volume");
   }
+  g->sp = solve_s_plan(g->S, g->N, g->M, g->dr, g->dc, g->ds);
   return SR3D_OK;
 }
 
@@ -174,20 +176,29 @@ struct TvWs {
   float *g;
   float2 *lam, *yh, *w, *w2;
   float *nu[2], *theta;
-  int nbS, nbF;
+  // fused x-update (when the geometry has a fused plan)
+  float2 *lamg, *yg;
+  int *tab;
+  SolveSArgs *sdesc;
+  int nbS, nbF, nbFold, nbFused;
+  bool fused;  // this solve uses the fused x-update (set by the caller)
 };
 
 // Workspace of one TV solve. nu[0] is only used when the caller passes no
-// state buffer.
+// state buffer. The fused x-update buffers exist whenever the geometry has a
+// fused plan, so the size does not depend on the flags.
 size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   Carve c{base, 0};
   L->nbS = stencil_plan(g.S, g.N, g.M).blocks;
   FoldArgs fa{};
   fa.Sl = g.Sl; fa.Nl = g.Nl; fa.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
-  L->nbF = fold_blocks(fa);
+  L->nbFold = fold_blocks(fa);
+  L->nbFused = g.sp.fused ? g.sp.units : 0;
+  L->nbF = L->nbFold;
+  L->fused = false;
   L->ctrl = c.take<Ctrl>(1);
   L->partS = c.take<double>((size_t)6 * L->nbS);
-  L->partF = c.take<double>((size_t)L->nbF);
+  L->partF = c.take<double>((size_t)(L->nbFold > L->nbFused ? L->nbFold : L->nbFused));
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
   L->lam = c.take<float2>(g.nspec);
   L->yh = c.take<float2>(g.nlspec);
@@ -196,7 +207,35 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->nu[0] = c.take<float>((size_t)3 * g.NH);
   L->nu[1] = c.take<float>((size_t)3 * g.NH);
   L->theta = c.take<float>(g.NH);
+  L->lamg = L->yg = nullptr;
+  L->tab = nullptr;
+  L->sdesc = nullptr;
+  if (g.sp.fused) {
+    L->lamg = c.take<float2>((size_t)g.sp.units * g.D * g.sp.gmax);
+    L->yg = c.take<float2>((size_t)g.sp.units * g.sp.gmax);
+    L->tab = c.take<int>(g.sp.tab.size());
+    L->sdesc = c.take<SolveSArgs>(1);
+  }
   return c.off + 256;
+}
+
+void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
+  L->fused = g.sp.fused && !(flags & SR3D_UNFUSED);
+  L->nbF = L->fused ? L->nbFused : L->nbFold;
+}
+
+SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem *p) {
+  SolveSArgs a{};
+  a.W = L.w; a.Lg = L.lamg; a.Yg = L.yg; a.tab = L.tab;
+  a.gm = L.g; a.gn = L.g + g.M; a.gs = L.g + g.M + g.N;
+  a.S = g.S; a.N = g.N; a.M = g.M; a.Mh = g.Mh; a.Sl = g.Sl; a.Nl = g.Nl; a.Ml = g.Ml;
+  a.dr = g.dr; a.dc = g.dc; a.ds = g.ds; a.D = g.D;
+  a.NG = g.sp.NG; a.NB = g.sp.NB; a.CB = g.sp.CB; a.gmax = g.sp.gmax; a.units = g.sp.units;
+  a.o_p0 = g.sp.o_p0; a.o_cnt = g.sp.o_cnt; a.o_mj = g.sp.o_mj; a.o_nj = g.sp.o_nj;
+  a.mu = p->mu;
+  a.scale = (float)(1.0 / (double)g.NH);
+  a.partial = L.partF; a.ctrl = L.ctrl; a.done = &L.ctrl->done;
+  return a;
 }
 
 struct TikWs {
@@ -278,6 +317,16 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   if ((e = fft3d_forward(L.theta, L.lam, g.S, g.N, g.M, nullptr, st))) return e;
   if ((e = fft3d_forward(p->y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st))) return e;
   if ((e = diff_tables(L.g, g.S, g.N, g.M, st))) return e;
+  if (L.fused) {
+    // Plan tables, the kernel's argument block, and Lambda / Y in unit order.
+    const SolveSArgs sa = make_solve_args(g, L, p);
+    if ((e = hipMemcpyAsync(L.tab, g.sp.tab.data(), sizeof(int) * g.sp.tab.size(),
+                            hipMemcpyHostToDevice, st)))
+      return e;
+    if ((e = hipMemcpyAsync(L.sdesc, &sa, sizeof sa, hipMemcpyHostToDevice, st))) return e;
+    if ((e = solve_s_gather(sa, L.lam, L.yh, g.Mlh, st))) return e;
+    if ((e = hipStreamSynchronize(st))) return e;  // the host images above are locals
+  }
   const float thr = p->lambda_tv / p->mu;
   if (flags & SR3D_RESUME) return theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st);
   const float *xinit = p->x0;
@@ -305,14 +354,24 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
                         int k, bool fp64, hipStream_t st) {
   const int *done = &L.ctrl->done;
   hipError_t e;
-  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
-  FoldArgs fa = make_fold(g);
-  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
-  fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
-  fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 1;
-  fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
-  if ((e = fold_solve(fa, fp64, st))) return e;
-  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  if (L.fused) {
+    const int *kofp = L.tab, *posk = L.tab + g.Mh;
+    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, done, st))) return e;
+    prof_begin(kStSolveS, st);
+    e = solve_s(g.S, g.sp.dm, L.sdesc, nullptr, g.sp.units, fp64, st);
+    prof_end(st);
+    if (e) return e;
+    if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, done, st))) return e;
+  } else {
+    if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+    FoldArgs fa = make_fold(g);
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+    fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 1;
+    fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+    if ((e = fold_solve(fa, fp64, st))) return e;
+    if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  }
   AdmmStencilArgs sa{};
   sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
@@ -335,6 +394,7 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   const size_t need = tv_layout(g, nullptr, &L);
   if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
   tv_layout(g, reinterpret_cast<char *>(ws), &L);
+  tv_choose_path(g, flags, &L);
   Ctrl *hc = host_ctrl();
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
   SR3D_TRY(ensure_device_tables(), "twiddle tables");
@@ -429,6 +489,7 @@ struct BatchHeader {
   RowDesc *r2c, *c2r;
   StridedDesc *fn, *in_, *fs, *is;
   FoldArgs *fold;
+  SolveSArgs *solve;
   BatchStencilDesc *sten;
   ReduceDesc *red;
   int *active;
@@ -445,6 +506,7 @@ size_t batch_header(int count, size_t nitems, char *base, BatchHeader *H) {
   H->fs = c.take<StridedDesc>(count);
   H->is = c.take<StridedDesc>(count);
   H->fold = c.take<FoldArgs>(count);
+  H->solve = c.take<SolveSArgs>(count);
   H->sten = c.take<BatchStencilDesc>(count);
   H->red = c.take<ReduceDesc>(count);
   H->active = c.take<int>(64);
@@ -453,8 +515,10 @@ size_t batch_header(int count, size_t nitems, char *base, BatchHeader *H) {
   return H->bytes;
 }
 
-// Items of every (stage, class) group for volumes with geometries g.
-size_t batch_items(const std::vector<Geometry> &g, BatchPlan *plan) {
+// Items of every (stage, class) group for volumes with geometries g; fused[v]
+// selects the fused x-update (kind 8, key S, variant = member bound) for
+// volume v instead of the s-FFTs and the fold.
+size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fused, BatchPlan *plan) {
   plan->groups.clear();
   auto group = [&](int kind, int key, int variant) -> BatchPlan::Group & {
     for (auto &x : plan->groups)
@@ -478,7 +542,7 @@ size_t batch_items(const std::vector<Geometry> &g, BatchPlan *plan) {
         tiles = strided_tiles(len, fft_variant(kind, len), (long)G.S * Mh);
       } else {
         len = G.S;
-        if (len == 1) continue;
+        if (len == 1 || fused[v]) continue;
         tiles = strided_tiles(len, fft_variant(kind, len), (long)G.N * Mh);
       }
       auto &gr = group(kind, len, fft_variant(kind, len));
@@ -486,6 +550,11 @@ size_t batch_items(const std::vector<Geometry> &g, BatchPlan *plan) {
     }
   }
   for (int v = 0; v < n; ++v) {
+    if (fused[v]) {
+      auto &gr = group(8, g[v].S, g[v].sp.dm);
+      for (int t = 0; t < g[v].sp.units; ++t) gr.items.push_back(make_int2(v, t));
+      continue;
+    }
     FoldArgs fa = make_fold(g[v]);
     auto &gr = group(6, g[v].D, 0);
     const int nb = fold_blocks(fa);
@@ -503,12 +572,21 @@ size_t batch_items(const std::vector<Geometry> &g, BatchPlan *plan) {
   return total;
 }
 
-size_t batch_workspace(const sr3d_problem *p, int count, std::vector<Geometry> *gs,
+// Workspace of a batch: header (descriptors and items) then one TV
+// workspace per volume. The header holds the larger of the fused and the
+// unfused item lists, so the size does not depend on the flags; `plan`
+// receives the items for `unfused`.
+size_t batch_workspace(const sr3d_problem *p, int count, bool unfused, std::vector<Geometry> *gs,
                        std::vector<size_t> *offs, BatchPlan *plan, size_t *header) {
   gs->resize(count);
   for (int i = 0; i < count; ++i)
     if (check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &(*gs)[i])) return 0;
-  const size_t nitems = batch_items(*gs, plan);
+  std::vector<char> fz(count), none(count, 0);
+  for (int i = 0; i < count; ++i) fz[i] = (*gs)[i].sp.fused ? 1 : 0;
+  BatchPlan other;
+  const size_t n_unf = batch_items(*gs, none, unfused ? plan : &other);
+  const size_t n_fus = batch_items(*gs, fz, unfused ? &other : plan);
+  const size_t nitems = n_unf > n_fus ? n_unf : n_fus;
   BatchHeader H;
   *header = batch_header(count, nitems, nullptr, &H);
   size_t off = (*header + 255) & ~(size_t)255;
@@ -553,7 +631,8 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
         const Geometry &G = g[v];
         hipError_t r = (kind == kFftR2cM)
                            ? launch_r2c_m_v(Ls[v].theta, Ls[v].w, (long)G.S * G.N, 1, 0, &Ls[v].ctrl->done, st)
-                           : launch_c2r_m_v(Ls[v].w2, p[v].x, (long)G.S * G.N, 1, 1.0f, 0, &Ls[v].ctrl->done, st);
+                           : launch_c2r_m_v(Ls[v].fused ? Ls[v].w : Ls[v].w2, p[v].x, (long)G.S * G.N, 1,
+                                            1.0f, 0, &Ls[v].ctrl->done, st);
         if (r != hipSuccess) return r;
       }
     return hipSuccess;
@@ -561,6 +640,13 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
   if ((e = run_fft(kFftR2cM, kStFftR2cM))) return e;
   if ((e = run_fft(kFftFwdN, kStFftN))) return e;
   if ((e = run_fft(kFftFwdS, kStFftS))) return e;
+  for (auto &gr : plan.groups) {
+    if (gr.kind != 8) continue;
+    prof_begin(kStSolveS, st);
+    e = solve_s(gr.key, gr.variant, H.solve, items_of(gr), (int)gr.items.size(), fp64, st);
+    prof_end(st);
+    if (e) return e;
+  }
   for (auto &gr : plan.groups) {
     if (gr.kind != 6) continue;
     prof_begin(kStFold, st);
@@ -596,7 +682,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   std::vector<size_t> offs;
   BatchPlan plan;
   size_t hdr = 0;
-  const size_t need = batch_workspace(p, count, &g, &offs, &plan, &hdr);
+  const size_t need = batch_workspace(p, count, (flags & SR3D_UNFUSED) != 0, &g, &offs, &plan, &hdr);
   if (!need) return fail(SR3D_ERR_INVALID_ARG, "invalid geometry");
   if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
   char *base = reinterpret_cast<char *>(ws);
@@ -605,7 +691,10 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   for (auto &gr : plan.groups) nitems += gr.items.size();
   batch_header(count, nitems, base, &H);
   std::vector<TvWs> Ls(count);
-  for (int i = 0; i < count; ++i) tv_layout(g[i], base + offs[i], &Ls[i]);
+  for (int i = 0; i < count; ++i) {
+    tv_layout(g[i], base + offs[i], &Ls[i]);
+    tv_choose_path(g[i], flags, &Ls[i]);
+  }
   Ctrl *hc = host_ctrl();
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
   SR3D_TRY(ensure_device_tables(), "twiddle tables");
@@ -616,6 +705,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   std::vector<RowDesc> r2c(count), c2r(count);
   std::vector<StridedDesc> fn(count), in_(count), fs(count), is(count);
   std::vector<FoldArgs> fold(count);
+  std::vector<SolveSArgs> solv(count);
   std::vector<BatchStencilDesc> sten(count);
   std::vector<ReduceDesc> red(count);
   std::vector<float *> nu0(count);
@@ -625,10 +715,12 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     const int *done = &L.ctrl->done;
     const long Mh = G.Mh;
     nu0[v] = p[v].state ? p[v].state : L.nu[0];
-    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done};
-    c2r[v] = RowDesc{nullptr, L.w2, p[v].x, (long)G.S * G.N, 1.0f, done};
+    const int *kofp = L.fused ? L.tab : nullptr, *posk = L.fused ? L.tab + G.Mh : nullptr;
+    float2 *xs = L.fused ? L.w : L.w2;  // spectrum of the x-update
+    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done, kofp, posk};
+    c2r[v] = RowDesc{nullptr, xs, p[v].x, (long)G.S * G.N, 1.0f, done, kofp, posk};
     fn[v] = make_strided_desc(L.w, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
-    in_[v] = make_strided_desc(L.w2, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
+    in_[v] = make_strided_desc(xs, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
     fs[v] = make_strided_desc(L.w, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
     is[v] = make_strided_desc(L.w2, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
     FoldArgs fa = make_fold(G);
@@ -637,6 +729,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     fa.cw = p[v].mu; fa.coefA = p[v].mu; fa.tv = 1;
     fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
     fold[v] = fa;
+    if (L.fused) solv[v] = make_solve_args(G, L, &p[v]);
     BatchStencilDesc sd{};
     sd.a.x = p[v].x; sd.a.theta = L.theta;
     sd.a.S = G.S; sd.a.N = G.N; sd.a.M = G.M; sd.a.thr = p[v].lambda_tv / p[v].mu;
@@ -664,6 +757,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   put(H.fs, fs.data(), sizeof(StridedDesc) * count);
   put(H.is, is.data(), sizeof(StridedDesc) * count);
   put(H.fold, fold.data(), sizeof(FoldArgs) * count);
+  put(H.solve, solv.data(), sizeof(SolveSArgs) * count);
   put(H.sten, sten.data(), sizeof(BatchStencilDesc) * count);
   put(H.red, red.data(), sizeof(ReduceDesc) * count);
   int active0 = count;
@@ -757,7 +851,7 @@ size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
     std::vector<size_t> offs;
     BatchPlan plan;
     size_t hdr = 0;
-    return batch_workspace(p, count, &gs, &offs, &plan, &hdr);
+    return batch_workspace(p, count, false, &gs, &offs, &plan, &hdr);
   }
   Geometry g;
   size_t total = 0;

@@ -246,11 +246,16 @@ int fft_tune_load(const char *path) {
 // ---------------------------------------------------------------------------
 
 static hipError_t run_kind(int kind, int stage, const float *rin, float *rout, float2 *spec, int S,
-                           int N, int M, float scale, const int *done, hipStream_t st) {
+                           int N, int M, float scale, const int *done, hipStream_t st,
+                           const int *kofp = nullptr, const int *posk = nullptr) {
   const int len = kind_len(kind, S, N, M);
   if (kind >= kFftFwdN && len == 1) return hipSuccess;
   prof_begin(stage, st);
-  hipError_t e = launch_kind(kind, fft_variant(kind, len), rin, rout, spec, S, N, M, scale, done, st);
+  hipError_t e;
+  const int v = fft_variant(kind, len);
+  if (kind == kFftR2cM) e = launch_r2c_m_v(rin, spec, (long)S * N, M, v, done, st, kofp, posk);
+  else if (kind == kFftC2rM) e = launch_c2r_m_v(spec, rout, (long)S * N, M, scale, v, done, st, kofp, posk);
+  else e = launch_kind(kind, v, rin, rout, spec, S, N, M, scale, done, st);
   prof_end(st);
   return e;
 }
@@ -268,6 +273,21 @@ hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float sc
   hipError_t e = run_kind(kFftInvS, kStIfftS, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
   if (e == hipSuccess) e = run_kind(kFftInvN, kStIfftN, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
   if (e == hipSuccess) e = run_kind(kFftC2rM, kStIfftC2rM, nullptr, out, spec, S, N, M, scale, done, st);
+  return e;
+}
+
+hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
+                            const int *posk, const int *done, hipStream_t st) {
+  hipError_t e = run_kind(kFftR2cM, kStFftR2cM, in, nullptr, spec, S, N, M, 1.0f, done, st, kofp, posk);
+  if (e == hipSuccess) e = run_kind(kFftFwdN, kStFftN, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
+  return e;
+}
+
+hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
+                            const int *kofp, const int *posk, const int *done, hipStream_t st) {
+  hipError_t e = run_kind(kFftInvN, kStIfftN, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
+  if (e == hipSuccess)
+    e = run_kind(kFftC2rM, kStIfftC2rM, nullptr, out, spec, S, N, M, scale, done, st, kofp, posk);
   return e;
 }
 

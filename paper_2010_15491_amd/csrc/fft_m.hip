@@ -15,11 +15,14 @@ template <int M, int E>
 __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
                                               const float2 *__restrict__ twh,
                                               const float2 *__restrict__ twm, float2 *lds,
-                                              float2 *stw) {
+                                              float2 *stw, int *sperm) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
   const long row0 = (long)bid * T;
   const long nrows = d.nrows;
   stage_twiddles<H>(stw, twh);
+  const bool perm = d.kofp != nullptr;
+  if (perm)
+    for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.kofp[i];
   const float2 *in2 = reinterpret_cast<const float2 *>(d.rin);
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int i = w % H, t = w / H;
@@ -30,16 +33,17 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
   fft_passes<H, T, TP, 0, 1>(lds, stw);
   float2 *out = d.spec;
   for (int w = threadIdx.x; w < MH * T; w += kThreads) {
-    const int k = w % MH, t = w / MH;
+    const int p = w % MH, t = w / MH;
     const long r = row0 + t;
     if (r < nrows) {
+      const int k = perm ? sperm[p] : p;
       const float2 zk = lds[(k % H) * TP + t];
       const float2 zm = lds[((H - k) % H) * TP + t];
       // E = (Z[k] + conj Z[H-k]) / 2 ; O = -i (Z[k] - conj Z[H-k]) / 2
       const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       const float2 wo = cmul(twm[k], o);
-      out[r * MH + k] = make_float2(e.x + wo.x, e.y + wo.y);
+      out[r * MH + p] = make_float2(e.x + wo.x, e.y + wo.y);
     }
   }
 }
@@ -48,19 +52,24 @@ template <int M, int E>
 __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
                                               const float2 *__restrict__ twh,
                                               const float2 *__restrict__ twm, float2 *lds,
-                                              float2 *stw) {
+                                              float2 *stw, int *sperm) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
   const long row0 = (long)bid * T;
   const long nrows = d.nrows;
   const float2 *in = d.spec;
   stage_twiddles<H>(stw, twh);
+  const bool perm = d.posk != nullptr;
+  if (perm) {
+    for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.posk[i];
+    __syncthreads();
+  }
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int k = w % H, t = w / H;
     const long r = row0 + t;
     float2 v = make_float2(0.f, 0.f);
     if (r < nrows) {
-      const float2 xk = in[r * MH + k];
-      const float2 xm = in[r * MH + (H - k)];
+      const float2 xk = in[r * MH + (perm ? sperm[k] : k)];
+      const float2 xm = in[r * MH + (perm ? sperm[H - k] : H - k)];
       // E = (X[k] + conj X[H-k]) / 2 ; O = e^{+2 pi i k/M} (X[k] - conj X[H-k]) / 2
       const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
       const float2 dd = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
@@ -148,8 +157,9 @@ __device__ __forceinline__ void row_body(const RowDesc &d, int bid, const float2
     constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1;
     __shared__ float2 lds[H * TP];
     __shared__ float2 stw[H];
-    if (C2R) c2r_half_body<M, E>(d, bid, twh, twm, lds, stw);
-    else r2c_half_body<M, E>(d, bid, twh, twm, lds, stw);
+    __shared__ int sperm[M / 2 + 1];
+    if (C2R) c2r_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm);
+    else r2c_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm);
   } else {
     constexpr int T = tile_lines(M, E), TP = T + 1;
     __shared__ float2 lds[M * TP];
@@ -264,24 +274,26 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
 }
 
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
-                          hipStream_t st) {
+                          hipStream_t st, const int *kofp, const int *posk) {
   if (M == 1) {
     hipLaunchKernelGGL(k_copy_r2c1, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, in,
                        out, nrows, done);
     return hipGetLastError();
   }
-  RowDesc d{in, out, nullptr, nrows, 1.0f, done};
+  if (M % 2) kofp = posk = nullptr;  // odd M: every class order is the natural one
+  RowDesc d{in, out, nullptr, nrows, 1.0f, done, kofp, posk};
   return launch_rows(d, M, false, v, st);
 }
 
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
-                          const int *done, hipStream_t st) {
+                          const int *done, hipStream_t st, const int *kofp, const int *posk) {
   if (M == 1) {
     hipLaunchKernelGGL(k_copy_c2r1, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, in,
                        out, nrows, scale, done);
     return hipGetLastError();
   }
-  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done};
+  if (M % 2) kofp = posk = nullptr;
+  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done, kofp, posk};
   return launch_rows(d, M, true, v, st);
 }
 

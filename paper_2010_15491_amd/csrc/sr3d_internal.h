@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "sr3d.h"
 
 namespace sr3d {
@@ -50,7 +52,7 @@ struct FastDiv {
 // launch on its stream when the calling thread has profiling switched on.
 enum Stage {
   kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
-  kStStencil, kStReduce, kStSetup, kStCount
+  kStStencil, kStReduce, kStSolveS, kStSetup, kStCount
 };
 void prof_begin(int stage, hipStream_t st);
 void prof_end(hipStream_t st);
@@ -89,6 +91,9 @@ struct RowDesc {
   long nrows;
   float scale;       // C2R output scale
   const int *done;
+  // Column order of the stored half spectrum (even M only): kofp[p] is the
+  // frequency k_m held at position p, posk its inverse. Null: natural order.
+  const int *kofp, *posk;
 };
 int strided_tiles(int L, int v, long ncols);
 int row_tiles(int M, int v, long nrows);
@@ -98,9 +103,10 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
                              int nitems, hipStream_t st);
 enum FftKind { kFftR2cM, kFftC2rM, kFftFwdN, kFftInvN, kFftFwdS, kFftInvS, kFftKinds };
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
-                          hipStream_t st);
+                          hipStream_t st, const int *kofp = nullptr, const int *posk = nullptr);
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
-                          const int *done, hipStream_t st);
+                          const int *done, hipStream_t st, const int *kofp = nullptr,
+                          const int *posk = nullptr);
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
                             long estride, bool inv, int v, const int *done, hipStream_t st);
 int fft_variant(int kind, int len);
@@ -122,6 +128,12 @@ hipError_t fft3d_forward(const float *in, float2 *spec, int S, int N, int M,
                          const int *done, hipStream_t st);
 hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                          const int *done, hipStream_t st);
+// The m and n passes alone (the s axis is left to the fused x-update), with
+// the m columns stored in the order kofp / posk.
+hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
+                            const int *posk, const int *done, hipStream_t st);
+hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
+                            const int *kofp, const int *posk, const int *done, hipStream_t st);
 
 // Fold / solve / unfold (eq. (8)-(12) and Algorithm 1 step 5a).
 struct FoldArgs {
@@ -147,6 +159,52 @@ hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
 hipError_t dual_init_spectrum(const FoldArgs &a, hipStream_t st);
 hipError_t fold_solve_batch(int D, const FoldArgs *descs, const int2 *items, int nitems, bool fp64,
                             hipStream_t st);
+
+// Fused x-update along s (solve_s.hip): one workgroup loads every s-line of
+// a set of (k_n, k_m) columns closed under aliasing and conjugation, does the
+// forward s-FFT, solves every alias group of those columns, does the inverse
+// s-FFT and writes the lines back. See SolveSPlan for the unit structure.
+struct SolveSArgs {
+  float2 *W;          // S x N x Mh spectrum after the m and n passes (m columns
+                      // in plan order); overwritten with the scaled x-update
+  const float2 *Lg;   // Lambda per (unit, member, slot)
+  const float2 *Yg;   // LR spectrum of y per (unit, slot)
+  const int *tab;     // plan tables (see SolveSPlan)
+  const float *gm, *gn, *gs;
+  int S, N, M, Mh, Sl, Nl, Ml;
+  int dr, dc, ds, D;
+  int NG, NB, CB, gmax, units;
+  int o_p0, o_cnt, o_mj, o_nj;
+  float mu, scale;
+  void *partial;      // data-term partial sums, one per unit (Acc)
+  Ctrl *ctrl;
+  const int *done;
+};
+// Unit structure. The LR columns (j_n, j_m) are split into n-groups (one
+// class {j_n, -j_n}, or the two self-conjugate classes {0} and {N_l/2}) and
+// m-blocks (CB consecutive classes {j_m, -j_m}); a unit is (n-group, m-block).
+// Its lines are the stored columns (k_n, k_m) with k_n mod N_l in the n-group
+// and k_m mod M_l in the m-block: every alias member of every group of the
+// unit, or its conjugate mirror, lies on one of them, and no other unit reads
+// or writes them. The m columns of a class are stored next to each other
+// (position order kofp), so each m-block is one contiguous run per row.
+struct SolveSPlan {
+  bool fused;   // the fused kernel handles this geometry
+  int dm;       // member-array bound of the kernel instance (8, 16 or 32)
+  int NG, NB, CB, units, gmax;
+  int o_p0, o_cnt, o_mj, o_nj;
+  // Host image of the device table:
+  //   kofp[Mh] | posk[Mh] | p0[NB] | cnt[NB] | mj[NB*CB] | nj[NG*2]
+  std::vector<int> tab;
+};
+// Plans the fused x-update for an S x N x M volume at rates (dr, dc, ds).
+SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds);
+hipError_t solve_s_gather(const SolveSArgs &a, const float2 *lam, const float2 *yh, int Mlh,
+                          hipStream_t st);
+// descs: device array of per-volume arguments; items: (volume, unit) per
+// workgroup, or null for one volume (descs[0]) with `units` workgroups.
+hipError_t solve_s(int S, int dm, const SolveSArgs *descs, const int2 *items, int nwg, bool fp64,
+                   hipStream_t st);
 
 // Fused difference / shrink / dual / Theta pass (Algorithm 1 steps 5b, 5c and
 // the Theta of the next 5a). State nu = L x + d_prev holds (u, d):

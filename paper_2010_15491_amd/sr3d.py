@@ -26,6 +26,7 @@ RESUME = 0x2
 USE_GRAPH = 0x4
 PROFILE = 0x8
 WARM_DUAL = 0x10
+UNFUSED = 0x20
 
 
 def CHECK_INTERVAL(k):

@@ -336,6 +336,73 @@ def test_batch_uneven_volumes_stop_like_single_solves(graph):
 
 
 # ---------------------------------------------------------------------------
+# Fused x-update (s-FFT + alias-group solve + inverse s-FFT in one kernel)
+# against the separate kernels and the oracle, on geometries that exercise
+# its unit structure: odd N_l, self-conjugate m classes, odd m, unequal class
+# sizes, single-sample axes, and an s-length outside the fused set.
+# ---------------------------------------------------------------------------
+
+
+def fit_psf(psf, shape):
+    """Central part of the PSF that fits the volume, renormalised to sum 1."""
+    sl = tuple(slice((k - min(k, n)) // 2, (k - min(k, n)) // 2 + min(k, n))
+               for k, n in zip(psf.shape, shape))
+    q = psf[sl]
+    return f32(q / q.sum())
+
+
+FUSE_CASES = [
+    ((16, 12, 12), (3, 4, 2)),
+    ((32, 16, 6), (3, 2, 2)),
+    ((48, 8, 3), (1, 1, 3)),
+    ((24, 6, 8), (4, 3, 1)),
+    ((32, 1, 32), (2, 1, 2)),
+    ((32, 16, 1), (1, 2, 2)),
+    ((8, 16, 16), (2, 2, 2)),
+    ((64, 32, 32), (2, 2, 4)),
+]
+
+
+@pytest.mark.parametrize("shape,rate", FUSE_CASES)
+def test_fused_and_unfused_x_update_match_oracle(shape, rate):
+    p = phantom.make_problem(shape, rate, 1.0, 0.02, 21, n_ellipsoids=6)
+    psf = fit_psf(p["psf"], shape)
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 8)
+    xf, sf = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 8)
+    xu, su = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 8,
+                          flags=sr3d.FP64_REDUCE | sr3d.UNFUSED)
+    ef, eu = O.rel_l2(host(xf), ref.x), O.rel_l2(host(xu), ref.x)
+    print(f"{shape} {rate}: fused {ef:.2e}, unfused {eu:.2e}")
+    assert ef < TOL and eu < TOL
+    assert O.rel_l2(host(xf), host(xu)) < 1e-6
+    assert np.isclose(sf.primal_rel, su.primal_rel, rtol=1e-4)
+    assert np.isclose(sf.objective, su.objective, rtol=1e-5)
+    assert np.isclose(sf.objective, O.tv_objective(host(xf), y, psf, rate, LAM_TV), rtol=1e-4)
+
+
+@pytest.mark.parametrize("unfused", [False, True])
+def test_batch_mixes_fused_and_unfused_volumes(unfused):
+    cases = [((8, 32, 32), (2, 2, 2)), ((32, 32, 32), (2, 2, 2)), ((16, 12, 12), (3, 4, 2)),
+             ((24, 6, 8), (4, 3, 1))]
+    flags = sr3d.FP64_REDUCE | (sr3d.UNFUSED if unfused else 0)
+    probs, refs = [], []
+    for i, (shape, rate) in enumerate(cases):
+        p = phantom.make_problem(shape, rate, 1.0, 0.02, 300 + i, n_ellipsoids=6)
+        psf = fit_psf(p["psf"], shape)
+        y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+        probs.append(dict(y=dev(y), psf=dev(psf), rate=rate, lam=LAM_TV, mu=MU, max_iter=12,
+                          tol=0.0))
+        refs.append(O.admm_tv(y, psf, rate, LAM_TV, MU, 12).x)
+    xs, sts = sr3d.batch(probs, flags=flags)
+    for x, st, ref, q in zip(xs, sts, refs, probs):
+        single, s1 = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 12, flags=flags)
+        assert st.iters == 12
+        assert O.rel_l2(host(x), host(single)) < 1e-6
+        assert O.rel_l2(host(x), ref) < TOL
+
+
+# ---------------------------------------------------------------------------
 # Full size (256^3, the benchmark workload): first iterate against the oracle,
 # invariants after the benchmark's iterations.
 # ---------------------------------------------------------------------------
