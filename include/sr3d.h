@@ -219,6 +219,11 @@ int sr3d_tune_load(const char *path);
 int sr3d_profile_read(int stage, const char **name, double *total_ms, long *launches);
 /* Clears the per-stage totals. */
 void sr3d_profile_reset(void);
+/* Restricts SR3D_PROFILE timing to the stages whose bit is set (bit i is
+ * stage index i of sr3d_profile_read); ~0u, the initial value, times every
+ * stage. Each timed launch adds two event records to the stream, so timing
+ * one stage disturbs a run less than timing all of them. Process-wide. */
+void sr3d_profile_select(unsigned stage_mask);
 
 /* Human-readable name of a status code. */
 const char *sr3d_status_string(int status);

@@ -29,6 +29,7 @@ thread_local ProfState t_prof;
 std::mutex g_prof_mu;
 double g_prof_ms[kStCount] = {0};
 long g_prof_n[kStCount] = {0};
+unsigned g_prof_mask = ~0u;  // stages timed under SR3D_PROFILE
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
                                      "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
                                      "reduce_test", "solve_s", "setup"};
@@ -37,6 +38,8 @@ const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fol
 void prof_begin(int stage, hipStream_t st) {
   ProfState &p = t_prof;
   if (!p.active) return;
+  const int recorded = p.override_stage >= 0 ? p.override_stage : stage;
+  if (!((g_prof_mask >> recorded) & 1u)) return;
   while (p.pool.size() < p.used + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) {
@@ -202,7 +205,8 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
   L->lam = c.take<float2>(g.nspec);
   L->yh = c.take<float2>(g.nlspec);
-  L->w = c.take<float2>(g.nspec);
+  // w holds the fused path's padded spectrum (rows g.sp.pitch apart) too
+  L->w = c.take<float2>(g.sp.fused ? (size_t)g.S * g.N * g.sp.pitch : (size_t)g.nspec);
   L->w2 = c.take<float2>(g.nspec);
   L->nu[0] = c.take<float>((size_t)3 * g.NH);
   L->nu[1] = c.take<float>((size_t)3 * g.NH);
@@ -229,6 +233,7 @@ SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem 
   a.W = L.w; a.Lg = L.lamg; a.Yg = L.yg; a.tab = L.tab;
   a.gm = L.g; a.gn = L.g + g.M; a.gs = L.g + g.M + g.N;
   a.S = g.S; a.N = g.N; a.M = g.M; a.Mh = g.Mh; a.Sl = g.Sl; a.Nl = g.Nl; a.Ml = g.Ml;
+  a.P = g.sp.pitch;
   a.dr = g.dr; a.dc = g.dc; a.ds = g.ds; a.D = g.D;
   a.NG = g.sp.NG; a.NB = g.sp.NB; a.CB = g.sp.CB; a.gmax = g.sp.gmax; a.units = g.sp.units;
   a.o_p0 = g.sp.o_p0; a.o_cnt = g.sp.o_cnt; a.o_mj = g.sp.o_mj; a.o_nj = g.sp.o_nj;
@@ -356,12 +361,14 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
   hipError_t e;
   if (L.fused) {
     const int *kofp = L.tab, *posk = L.tab + g.Mh;
-    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, done, st))) return e;
+    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st)))
+      return e;
     prof_begin(kStSolveS, st);
     e = solve_s(g.S, g.sp.dm, L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
-    if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, done, st))) return e;
+    if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
+      return e;
   } else {
     if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
     FoldArgs fa = make_fold(g);
@@ -539,7 +546,7 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
       } else if (kind == kFftFwdN || kind == kFftInvN) {
         len = G.N;
         if (len == 1) continue;
-        tiles = strided_tiles(len, fft_variant(kind, len), (long)G.S * Mh);
+        tiles = strided_tiles(len, fft_variant(kind, len), (long)G.S * (fused[v] ? G.sp.pitch : Mh));
       } else {
         len = G.S;
         if (len == 1 || fused[v]) continue;
@@ -717,10 +724,11 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     nu0[v] = p[v].state ? p[v].state : L.nu[0];
     const int *kofp = L.fused ? L.tab : nullptr, *posk = L.fused ? L.tab + G.Mh : nullptr;
     float2 *xs = L.fused ? L.w : L.w2;  // spectrum of the x-update
-    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done, kofp, posk};
-    c2r[v] = RowDesc{nullptr, xs, p[v].x, (long)G.S * G.N, 1.0f, done, kofp, posk};
-    fn[v] = make_strided_desc(L.w, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
-    in_[v] = make_strided_desc(xs, (long)G.S * Mh, Mh, (long)G.N * Mh, Mh, done);
+    const long P = L.fused ? G.sp.pitch : Mh;  // spectrum row pitch
+    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P};
+    c2r[v] = RowDesc{nullptr, xs, p[v].x, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P};
+    fn[v] = make_strided_desc(L.w, (long)G.S * P, P, (long)G.N * P, P, done, Mh);
+    in_[v] = make_strided_desc(xs, (long)G.S * P, P, (long)G.N * P, P, done, Mh);
     fs[v] = make_strided_desc(L.w, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
     is[v] = make_strided_desc(L.w2, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);
     FoldArgs fa = make_fold(G);
@@ -1111,6 +1119,11 @@ int sr3d_profile_read(int stage, const char **name, double *total_ms, long *laun
   if (total_ms) *total_ms = g_prof_ms[stage];
   if (launches) *launches = g_prof_n[stage];
   return SR3D_OK;
+}
+
+void sr3d_profile_select(unsigned stage_mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_mask = stage_mask;
 }
 
 void sr3d_profile_reset(void) {

@@ -246,16 +246,11 @@ int fft_tune_load(const char *path) {
 // ---------------------------------------------------------------------------
 
 static hipError_t run_kind(int kind, int stage, const float *rin, float *rout, float2 *spec, int S,
-                           int N, int M, float scale, const int *done, hipStream_t st,
-                           const int *kofp = nullptr, const int *posk = nullptr) {
+                           int N, int M, float scale, const int *done, hipStream_t st) {
   const int len = kind_len(kind, S, N, M);
   if (kind >= kFftFwdN && len == 1) return hipSuccess;
   prof_begin(stage, st);
-  hipError_t e;
-  const int v = fft_variant(kind, len);
-  if (kind == kFftR2cM) e = launch_r2c_m_v(rin, spec, (long)S * N, M, v, done, st, kofp, posk);
-  else if (kind == kFftC2rM) e = launch_c2r_m_v(spec, rout, (long)S * N, M, scale, v, done, st, kofp, posk);
-  else e = launch_kind(kind, v, rin, rout, spec, S, N, M, scale, done, st);
+  hipError_t e = launch_kind(kind, fft_variant(kind, len), rin, rout, spec, S, N, M, scale, done, st);
   prof_end(st);
   return e;
 }
@@ -276,18 +271,38 @@ hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float sc
   return e;
 }
 
+// n-axis pass over a spectrum with rows `pitch` apart (padding columns skipped).
+static hipError_t run_n_pitched(bool inv, float2 *spec, int S, int N, int M, int pitch,
+                                const int *done, hipStream_t st) {
+  if (N == 1) return hipSuccess;
+  const int kind = inv ? kFftInvN : kFftFwdN;
+  prof_begin(inv ? kStIfftN : kStFftN, st);
+  const hipError_t e = launch_strided_v(spec, N, (long)S * pitch, pitch, (long)N * pitch, pitch,
+                                        inv, fft_variant(kind, N), done, st, M / 2 + 1);
+  prof_end(st);
+  return e;
+}
+
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
-                            const int *posk, const int *done, hipStream_t st) {
-  hipError_t e = run_kind(kFftR2cM, kStFftR2cM, in, nullptr, spec, S, N, M, 1.0f, done, st, kofp, posk);
-  if (e == hipSuccess) e = run_kind(kFftFwdN, kStFftN, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
+                            const int *posk, int pitch, const int *done, hipStream_t st) {
+  prof_begin(kStFftR2cM, st);
+  hipError_t e = launch_r2c_m_v(in, spec, (long)S * N, M, fft_variant(kFftR2cM, M), done, st,
+                                kofp, posk, pitch);
+  prof_end(st);
+  if (e == hipSuccess) e = run_n_pitched(false, spec, S, N, M, pitch, done, st);
   return e;
 }
 
 hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
-                            const int *kofp, const int *posk, const int *done, hipStream_t st) {
-  hipError_t e = run_kind(kFftInvN, kStIfftN, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);
-  if (e == hipSuccess)
-    e = run_kind(kFftC2rM, kStIfftC2rM, nullptr, out, spec, S, N, M, scale, done, st, kofp, posk);
+                            const int *kofp, const int *posk, int pitch, const int *done,
+                            hipStream_t st) {
+  hipError_t e = run_n_pitched(true, spec, S, N, M, pitch, done, st);
+  if (e == hipSuccess) {
+    prof_begin(kStIfftC2rM, st);
+    e = launch_c2r_m_v(spec, out, (long)S * N, M, scale, fft_variant(kFftC2rM, M), done, st,
+                       kofp, posk, pitch);
+    prof_end(st);
+  }
   return e;
 }
 

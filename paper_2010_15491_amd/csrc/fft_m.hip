@@ -21,6 +21,7 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
   const long nrows = d.nrows;
   stage_twiddles<H>(stw, twh);
   const bool perm = d.kofp != nullptr;
+  const long pitch = d.pitch ? d.pitch : MH;
   if (perm)
     for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.kofp[i];
   const float2 *in2 = reinterpret_cast<const float2 *>(d.rin);
@@ -43,7 +44,7 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
       const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       const float2 wo = cmul(twm[k], o);
-      out[r * MH + p] = make_float2(e.x + wo.x, e.y + wo.y);
+      out[r * pitch + p] = make_float2(e.x + wo.x, e.y + wo.y);
     }
   }
 }
@@ -59,6 +60,7 @@ __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
   const float2 *in = d.spec;
   stage_twiddles<H>(stw, twh);
   const bool perm = d.posk != nullptr;
+  const long pitch = d.pitch ? d.pitch : MH;
   if (perm) {
     for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.posk[i];
     __syncthreads();
@@ -68,8 +70,8 @@ __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
     const long r = row0 + t;
     float2 v = make_float2(0.f, 0.f);
     if (r < nrows) {
-      const float2 xk = in[r * MH + (perm ? sperm[k] : k)];
-      const float2 xm = in[r * MH + (perm ? sperm[H - k] : H - k)];
+      const float2 xk = in[r * pitch + (perm ? sperm[k] : k)];
+      const float2 xm = in[r * pitch + (perm ? sperm[H - k] : H - k)];
       // E = (X[k] + conj X[H-k]) / 2 ; O = e^{+2 pi i k/M} (X[k] - conj X[H-k]) / 2
       const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
       const float2 dd = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
@@ -114,7 +116,7 @@ __device__ __forceinline__ void r2c_full_body(const RowDesc &d, int bid,
   for (int w = threadIdx.x; w < MH * T; w += kThreads) {
     const int k = w % MH, t = w / MH;
     const long r = row0 + t;
-    if (r < nrows) d.spec[r * MH + k] = lds[k * TP + t];
+    if (r < nrows) d.spec[r * (d.pitch ? d.pitch : MH) + k] = lds[k * TP + t];
   }
 }
 
@@ -131,11 +133,12 @@ __device__ __forceinline__ void c2r_full_body(const RowDesc &d, int bid,
     const long r = row0 + t;
     float2 v = make_float2(0.f, 0.f);
     if (r < nrows) {
+      const long rp = r * (d.pitch ? d.pitch : MH);
       if (k < MH) {
-        v = d.spec[r * MH + k];
+        v = d.spec[rp + k];
         v.y = -v.y;
       } else {
-        v = d.spec[r * MH + (M - k)];
+        v = d.spec[rp + (M - k)];
       }
     }
     lds[k * TP + t] = v;
@@ -274,26 +277,29 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
 }
 
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
-                          hipStream_t st, const int *kofp, const int *posk) {
+                          hipStream_t st, const int *kofp, const int *posk, int pitch) {
   if (M == 1) {
+    if (pitch > 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy_r2c1, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, in,
                        out, nrows, done);
     return hipGetLastError();
   }
   if (M % 2) kofp = posk = nullptr;  // odd M: every class order is the natural one
-  RowDesc d{in, out, nullptr, nrows, 1.0f, done, kofp, posk};
+  RowDesc d{in, out, nullptr, nrows, 1.0f, done, kofp, posk, pitch};
   return launch_rows(d, M, false, v, st);
 }
 
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
-                          const int *done, hipStream_t st, const int *kofp, const int *posk) {
+                          const int *done, hipStream_t st, const int *kofp, const int *posk,
+                          int pitch) {
   if (M == 1) {
+    if (pitch > 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy_c2r1, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, in,
                        out, nrows, scale, done);
     return hipGetLastError();
   }
   if (M % 2) kofp = posk = nullptr;
-  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done, kofp, posk};
+  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done, kofp, posk, pitch};
   return launch_rows(d, M, true, v, st);
 }
 

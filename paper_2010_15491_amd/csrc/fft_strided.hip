@@ -2,7 +2,8 @@
 //
 // Column c (0 <= c < ncols) of the launch starts at
 // (c / inner) * outer_stride + (c % inner) and its element i lies i * estride
-// further. A workgroup takes T adjacent columns, so every element row it
+// further; columns with c % inner >= inner_valid are row padding and are
+// neither read nor written. A workgroup takes T adjacent columns, so every element row it
 // moves is T consecutive complex values; the lines are transformed in LDS
 // (t fastest across lanes) and written back to the same places.
 #include "fft_core.h"
@@ -16,11 +17,13 @@ __device__ __forceinline__ void strided_body(const StridedDesc &d, int bid,
   constexpr int T = tile_lines(N, E);
   const int t = threadIdx.x % T;  // fixed per thread since T divides kThreads
   const int c = bid * T + t;
-  const bool valid = c < d.ncols;
+  bool valid = c < d.ncols;
   long base = 0;
   if (valid) {
     const uint32_t q = d.inner.div((uint32_t)c);
-    base = (long)q * d.outer_stride + (long)(c - q * d.inner.d);
+    const int r = (int)(c - q * d.inner.d);
+    valid = r < d.inner_valid;
+    base = (long)q * d.outer_stride + r;
   }
   float2 *data = d.data;
   const long estride = d.estride;
@@ -121,10 +124,12 @@ hipError_t launch_strided_batch(int L, bool inv, int v, const StridedDesc *descs
 }
 
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
-                            long estride, bool inv, int v, const int *done, hipStream_t st) {
+                            long estride, bool inv, int v, const int *done, hipStream_t st,
+                            long inner_valid) {
   if (L == 1) return hipSuccess;
   if (!twiddles(L)) return hipErrorInvalidValue;
-  const StridedDesc d = make_strided_desc(data, ncols, inner, outer_stride, estride, done);
+  const StridedDesc d =
+      make_strided_desc(data, ncols, inner, outer_stride, estride, done, inner_valid);
   switch (L) {
 #define SR3D_CASE(LL)                                                           \
   case LL:                                                                      \

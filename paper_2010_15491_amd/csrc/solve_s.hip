@@ -22,7 +22,12 @@
 
 namespace sr3d {
 
-constexpr int kSolveTile = 8192;  // complex s-line elements per workgroup
+// Lines per workgroup: as many as fit two workgroups in a CU's 160 KB of LDS
+// (lines, twiddles, |sigma_s|^2 table and side tables), at most 64.
+constexpr int solve_tile(int S) {
+  const int t = (81920 - 12 * S - 2048) / (8 * S);
+  return t > 64 ? 64 : t;
+}
 
 #define SR3D_SOLVE_S_LENGTHS(X) \
   X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -49,7 +54,7 @@ SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds) {
   if (!solve_s_len(S) || D > 32) return P;
   P.dm = D <= 8 ? 8 : D <= 16 ? 16 : 32;
   const int Sl = S / ds, Nl = N / dc, Ml = M / dr, Mh = M / 2 + 1;
-  const int T = tile_lines(S, kSolveTile);
+  const int T = solve_tile(S);
   // m classes {j, -j mod M_l}, representative j <= M_l - j; each holds the
   // stored k_m (< Mh) congruent to j or -j, in increasing k_m.
   const int NC = Ml / 2 + 1;
@@ -81,11 +86,24 @@ SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds) {
   }
   const int NG = (int)nj.size() / 2;
   const int rows_max = (nj[1] >= 0 || NG > 1) ? 2 * dc : dc;
-  const int KM = T / rows_max;
-  int CB = KM / csize;
-  if (CB < 1) return P;
-  if (CB > NC) CB = NC;
-  const int NB = (NC + CB - 1) / CB;
+  const int KM = T / rows_max;  // stored m columns per unit
+  if (KM < csize) return P;
+  // m-blocks: consecutive classes, greedily, while the columns fit.
+  std::vector<int> bstart;
+  int cols = KM + 1;
+  for (int j = 0; j < NC; ++j) {
+    const int sz = (int)cls[j].size();
+    if (cols + sz > KM) {
+      bstart.push_back(j);
+      cols = 0;
+    }
+    cols += sz;
+  }
+  const int NB = (int)bstart.size();
+  bstart.push_back(NC);
+  int CB = 1;
+  for (int b = 0; b < NB; ++b) CB = bstart[b + 1] - bstart[b] > CB ? bstart[b + 1] - bstart[b] : CB;
+  if (CB * dr > 64) return P;
   P.NG = NG;
   P.NB = NB;
   P.CB = CB;
@@ -100,10 +118,8 @@ SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds) {
   for (int b = 0; b < NB; ++b) {
     P.tab[P.o_p0 + b] = pos;
     int cnt = 0;
-    for (int c = 0; c < CB; ++c) {
-      const int j = b * CB + c;
-      if (j >= NC) break;
-      P.tab[P.o_mj + b * CB + c] = j;
+    for (int j = bstart[b]; j < bstart[b + 1]; ++j) {
+      P.tab[P.o_mj + b * CB + (j - bstart[b])] = j;
       for (int k : cls[j]) {
         P.tab[pos] = k;       // kofp
         P.tab[Mh + k] = pos;  // posk
@@ -114,6 +130,9 @@ SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds) {
     P.tab[P.o_cnt + b] = cnt;
   }
   for (int i = 0; i < 2 * NG; ++i) P.tab[P.o_nj + i] = nj[i];
+  // Long rows are padded to a multiple of 16 complex values (128 bytes), so
+  // row starts and the n-pass tiles are cache-line aligned.
+  P.pitch = Mh >= 64 ? (Mh + 15) / 16 * 16 : Mh;
   P.fused = true;
   return P;
 }
@@ -169,14 +188,20 @@ __device__ __forceinline__ int solve_xcd_unit(int b, int nb) {
   return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
-// Group of slot `slot` of unit u: returns false for an empty or skipped slot.
+// Group of slot `slot` of a unit whose m-block has nc classes (slots
+// 0 .. 2 S_l nc - 1): returns false for an empty or skipped slot.
 struct SlotGroup {
   int js, jn, jm, ji, ci;
   bool selfc;
 };
-__device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, int j0, int j1,
-                                           int slot, SlotGroup &g) {
-  const int ci = slot % a.CB, r1 = slot / a.CB;
+__device__ __forceinline__ int block_classes(const int *mj, int CB) {
+  int nc = 0;
+  while (nc < CB && mj[nc] >= 0) ++nc;
+  return nc;
+}
+__device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, int nc, int j0,
+                                           int j1, int slot, SlotGroup &g) {
+  const int ci = slot % nc, r1 = slot / nc;
   const int ji = r1 & 1, js = r1 >> 1;
   const int jm = mj[ci];
   if (jm < 0 || (ji && j1 < 0)) return false;
@@ -204,7 +229,9 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
   const int gn = u / a.NB, bm = u - gn * a.NB;
   const int j0 = a.tab[a.o_nj + 2 * gn], j1 = a.tab[a.o_nj + 2 * gn + 1];
   SlotGroup g;
-  if (!slot_group(a, a.tab + a.o_mj + bm * a.CB, j0, j1, slot, g)) {
+  const int *mj = a.tab + a.o_mj + bm * a.CB;
+  const int nc = block_classes(mj, a.CB);
+  if (slot >= a.Sl * 2 * nc || !slot_group(a, mj, nc, j0, j1, slot, g)) {
     Yg[i] = make_float2(0.f, 0.f);
     for (int q = 0; q < a.D; ++q) Lg[((long)u * a.D + q) * a.gmax + slot] = make_float2(0.f, 0.f);
     return;
@@ -243,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
 struct UnitTabs {
   int loff[64];     // global offset of line l within an s-plane, or -1
   int mj[64];       // class representatives j_m of the m-block (-1: none)
+  int nc;           // classes in the m-block
   int mpos[64];     // (ci, a): line position of the stored rep of k_m, bit 30 = mirrored
   float gmv[64];    // (ci, a): |sigma_m(k_m)|^2
   int rowd[64];     // (ji, b): row of k_n
@@ -254,7 +282,7 @@ template <int S, int DM, typename Acc>
 __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
                                              const float2 *__restrict__ tw, float2 *lds,
                                              float2 *stw, float *sgs, UnitTabs &ut, Acc *red) {
-  constexpr int T = tile_lines(S, kSolveTile), TP = T + 1;
+  constexpr int T = solve_tile(S), TP = T;
   const int gn = u / a.NB, bm = u - gn * a.NB;
   cgint *tab = (cgint *)a.tab;
   cgfloat *gmt = (cgfloat *)a.gm, *gnt = (cgfloat *)a.gn, *gst = (cgfloat *)a.gs;
@@ -262,7 +290,7 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   const int j0 = tab[a.o_nj + 2 * gn], j1 = tab[a.o_nj + 2 * gn + 1];
   const int nji = j1 < 0 ? 1 : 2;
   const int nlines = nji * a.dc * cnt;
-  const long plane = (long)a.N * a.Mh;
+  const long plane = (long)a.N * a.P;
   stage_twiddles<S>(stw, tw);
   for (int i = threadIdx.x; i < S; i += kThreads) sgs[i] = gst[i];
   {
@@ -272,11 +300,16 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
       if (t < nlines) {
         const int row = t / cnt, pp = t - row * cnt;
         const int ji = row / a.dc, b = row - ji * a.dc;
-        off = ((ji ? j1 : j0) + b * a.Nl) * a.Mh + p0 + pp;
+        off = ((ji ? j1 : j0) + b * a.Nl) * a.P + p0 + pp;
       }
       ut.loff[t] = off;
     }
     if (t < a.CB) ut.mj[t] = tab[a.o_mj + bm * a.CB + t];
+    if (t == 0) {
+      int nc = 0;
+      while (nc < a.CB && tab[a.o_mj + bm * a.CB + nc] >= 0) ++nc;
+      ut.nc = nc;
+    }
     if (t < a.CB * a.dr) {
       const int ci = t / a.dr, ia = t - ci * a.dr;
       const int jm = tab[a.o_mj + bm * a.CB + ci];
@@ -300,27 +333,28 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     }
   }
   __syncthreads();
-  // Each thread keeps one line (T divides the workgroup) and every
-  // (kThreads / T)-th plane: all its loads are issued before the first use.
-  constexpr int SPT = S * T / kThreads, SSTEP = kThreads / T;
-  static_assert(SPT * kThreads == S * T, "tile must divide evenly");
-  const int myline = threadIdx.x % T, s0 = threadIdx.x / T;
-  const int myoff = ut.loff[myline];
-  // byte offsets fit 32 bits (the spectrum is below 2^31 complex values)
-  const uint32_t gstep = (uint32_t)(SSTEP * plane) * 8u;
-  const uint32_t goff0 = ((uint32_t)(s0 * plane) + (uint32_t)myoff) * 8u;
-  float2 *lrow = lds + s0 * TP + myline;  // element k at lrow[k * SSTEP * TP]
-  {
-    float2 v[SPT];
-    if (myoff >= 0) {
+  // Element w of the tile is (s, line) = (w / T, w % T), at lds[w]. All of a
+  // thread's loads are issued before the first LDS store; lines past the
+  // unit's load element 0 and are zeroed.
+  constexpr int NE = (S * T + kThreads - 1) / kThreads;
+  constexpr int NH = (NE + 1) / 2;  // loads in flight per thread: half the tile
+  const uint32_t pl = (uint32_t)plane;
 #pragma unroll
-      for (int k = 0; k < SPT; ++k) v[k] = gld2(a.W, goff0 + k * gstep);
-    } else {
+  for (int h = 0; h < NE; h += NH) {
+    float2 v[NH];
 #pragma unroll
-      for (int k = 0; k < SPT; ++k) v[k] = make_float2(0.f, 0.f);
+    for (int k = 0; k < NH; ++k) {
+      const int w = threadIdx.x + (h + k) * kThreads;
+      const int s = w / T, line = w - s * T;
+      const int off = (h + k < NE && w < S * T) ? ut.loff[line] : -1;
+      const float2 x = gld2(a.W, ((uint32_t)(off >= 0 ? s : 0) * pl + (uint32_t)(off >= 0 ? off : 0)) * 8u);
+      v[k] = off >= 0 ? x : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) lrow[k * SSTEP * TP] = v[k];
+    for (int k = 0; k < NH; ++k) {
+      const int w = threadIdx.x + (h + k) * kThreads;
+      if (h + k < NE && w < S * T) lds[w] = v[k];
+    }
   }
   __syncthreads();
   fft_passes<S, T, TP, 0, 1>(lds, stw);
@@ -334,26 +368,27 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   cgu64 *Yu = (cgu64 *)a.Yg + (long)u * a.gmax;
   // Lambda and Y of the next slot are loaded while the current one is solved.
   float2 lnext[DM], ynext = make_float2(0.f, 0.f);
-  if ((int)threadIdx.x < a.gmax) {
+  const int nc = ut.nc, gcount = a.Sl * 2 * nc;  // slots of this unit
+  if ((int)threadIdx.x < gcount) {
     ynext = u64_f2(Yu[threadIdx.x]);
 #pragma unroll
     for (int q = 0; q < DM; ++q)
       if (q < a.D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + threadIdx.x]);
   }
-  for (int slot = threadIdx.x; slot < a.gmax; slot += kThreads) {
+  for (int slot = threadIdx.x; slot < gcount; slot += kThreads) {
     float2 lcur[DM];
 #pragma unroll
     for (int q = 0; q < DM; ++q) lcur[q] = lnext[q];
     const float2 Yj = ynext;
     const int nslot = slot + kThreads;
-    if (nslot < a.gmax) {
+    if (nslot < gcount) {
       ynext = u64_f2(Yu[nslot]);
 #pragma unroll
       for (int q = 0; q < DM; ++q)
         if (q < a.D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
     }
     SlotGroup g;
-    if (!slot_group(a, ut.mj, j0, j1, slot, g)) continue;
+    if (!slot_group(a, ut.mj, nc, j0, j1, slot, g)) continue;
     // Members: Lambda, B = conj(Lambda) Y + mu W, A = mu G, the LDS index of
     // the stored entry (li >= 0: the member itself, else -1-index of its
     // mirror) and, for a stored member whose -k is stored as well and belongs
@@ -490,11 +525,18 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   }
   __syncthreads();
   fft_passes<S, T, TP, 0, 1>(lds, stw);
-  if (myoff >= 0) {
+  // The tile indices are recomputed here rather than kept live from the load
+  // phase (an empty asm hides that this is the same thread index).
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      const float2 v = lrow[k * SSTEP * TP];
-      gst2(a.W, goff0 + k * gstep, make_float2(v.x, -v.y));
+  for (int k = 0; k < NE; ++k) {
+    const int w = tid + k * kThreads;
+    const int s = w / T, line = w - s * T;
+    const int off = (w < S * T) ? ut.loff[line] : -1;
+    if (off >= 0) {
+      const float2 v = lds[w];
+      gst2(a.W, ((uint32_t)s * pl + (uint32_t)off) * 8u, make_float2(v.x, -v.y));
     }
   }
   if (a.partial) {
@@ -518,8 +560,8 @@ __global__ __launch_bounds__(kThreads, (DM <= 8 ? 2 : 1)) void k_solve_s(const S
   }
   const SolveSArgs a = descs[v];
   if (a.done && *a.done) return;
-  constexpr int T = tile_lines(S, kSolveTile);
-  __shared__ float2 lds[S * (T + 1)];
+  constexpr int T = solve_tile(S);
+  __shared__ float2 lds[S * T];
   __shared__ float2 stw[S];
   __shared__ float sgs[S];
   __shared__ UnitTabs ut;

@@ -70,15 +70,17 @@ struct StridedDesc {
   float2 *data;
   int ncols;
   FastDiv inner;
+  int inner_valid;  // columns with (c mod inner) >= inner_valid are row padding: skipped
   long outer_stride, estride;
   const int *done;
 };
 inline StridedDesc make_strided_desc(float2 *data, long ncols, long inner, long outer_stride,
-                                     long estride, const int *done) {
+                                     long estride, const int *done, long inner_valid = -1) {
   StridedDesc d;
   d.data = data;
   d.ncols = (int)ncols;
   d.inner = FastDiv((uint32_t)inner);
+  d.inner_valid = (int)(inner_valid < 0 ? inner : inner_valid);
   d.outer_stride = outer_stride;
   d.estride = estride;
   d.done = done;
@@ -94,6 +96,7 @@ struct RowDesc {
   // Column order of the stored half spectrum (even M only): kofp[p] is the
   // frequency k_m held at position p, posk its inverse. Null: natural order.
   const int *kofp, *posk;
+  int pitch;  // complex entries between spectrum rows (0: M/2 + 1)
 };
 int strided_tiles(int L, int v, long ncols);
 int row_tiles(int M, int v, long nrows);
@@ -103,12 +106,14 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
                              int nitems, hipStream_t st);
 enum FftKind { kFftR2cM, kFftC2rM, kFftFwdN, kFftInvN, kFftFwdS, kFftInvS, kFftKinds };
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
-                          hipStream_t st, const int *kofp = nullptr, const int *posk = nullptr);
+                          hipStream_t st, const int *kofp = nullptr, const int *posk = nullptr,
+                          int pitch = 0);
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
                           const int *done, hipStream_t st, const int *kofp = nullptr,
-                          const int *posk = nullptr);
+                          const int *posk = nullptr, int pitch = 0);
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
-                            long estride, bool inv, int v, const int *done, hipStream_t st);
+                            long estride, bool inv, int v, const int *done, hipStream_t st,
+                            long inner_valid = -1);
 int fft_variant(int kind, int len);
 void fft_set_variant(int kind, int len, int v);
 // Times every tile variant of every axis kernel a volume S x N x M uses and
@@ -129,11 +134,12 @@ hipError_t fft3d_forward(const float *in, float2 *spec, int S, int N, int M,
 hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                          const int *done, hipStream_t st);
 // The m and n passes alone (the s axis is left to the fused x-update), with
-// the m columns stored in the order kofp / posk.
+// the m columns stored in the order kofp / posk and rows `pitch` apart.
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
-                            const int *posk, const int *done, hipStream_t st);
+                            const int *posk, int pitch, const int *done, hipStream_t st);
 hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
-                            const int *kofp, const int *posk, const int *done, hipStream_t st);
+                            const int *kofp, const int *posk, int pitch, const int *done,
+                            hipStream_t st);
 
 // Fold / solve / unfold (eq. (8)-(12) and Algorithm 1 step 5a).
 struct FoldArgs {
@@ -172,6 +178,7 @@ struct SolveSArgs {
   const int *tab;     // plan tables (see SolveSPlan)
   const float *gm, *gn, *gs;
   int S, N, M, Mh, Sl, Nl, Ml;
+  int P;              // row pitch of W (complex entries)
   int dr, dc, ds, D;
   int NG, NB, CB, gmax, units;
   int o_p0, o_cnt, o_mj, o_nj;
@@ -191,6 +198,7 @@ struct SolveSArgs {
 struct SolveSPlan {
   bool fused;   // the fused kernel handles this geometry
   int dm;       // member-array bound of the kernel instance (8, 16 or 32)
+  int pitch;    // row pitch of the spectrum (Mh rounded up to 16 for long rows)
   int NG, NB, CB, units, gmax;
   int o_p0, o_cnt, o_mj, o_nj;
   // Host image of the device table:

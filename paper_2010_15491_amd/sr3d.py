@@ -41,7 +41,8 @@ EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
            "sr3d_cnn_adam", "sr3d_conv3d_workspace_size", "sr3d_conv3d_forward",
            "sr3d_conv3d_backward", "sr3d_autotune",
            "sr3d_tune_save", "sr3d_tune_load", "sr3d_profile_read",
-           "sr3d_profile_reset", "sr3d_status_string", "sr3d_last_error", "sr3d_shutdown"]
+           "sr3d_profile_reset", "sr3d_profile_select", "sr3d_status_string", "sr3d_last_error",
+           "sr3d_shutdown"]
 
 
 class Dims(ctypes.Structure):
@@ -130,6 +131,8 @@ def load():
         lib.sr3d_profile_read.restype = ci
         lib.sr3d_profile_reset.argtypes = []
         lib.sr3d_profile_reset.restype = None
+        lib.sr3d_profile_select.argtypes = [ctypes.c_uint]
+        lib.sr3d_profile_select.restype = None
         lib.sr3d_shutdown.argtypes = []
         lib.sr3d_shutdown.restype = None
         _lib = lib
@@ -469,6 +472,25 @@ def profile_read():
         out[name.value.decode()] = (ms.value, n.value)
         i += 1
     return out
+
+
+def profile_select(stages=None):
+    """Time only the named stages under PROFILE (None: every stage)."""
+    lib = load()
+    if stages is None:
+        mask = 0xFFFFFFFF
+    else:
+        names, i = {}, 0
+        while True:
+            name = ctypes.c_char_p()
+            if lib.sr3d_profile_read(i, ctypes.byref(name), None, None) != 0:
+                break
+            names[name.value.decode()] = i
+            i += 1
+        mask = 0
+        for st in stages:
+            mask |= 1 << names[st]
+    lib.sr3d_profile_select(ctypes.c_uint(mask))
 
 
 def shutdown():
