@@ -87,7 +87,9 @@ typedef struct {
  * initial state and x0 is ignored (checkpoint / resume). */
 
 /* flags for sr3d_tv_admm / sr3d_batch */
-#define SR3D_FP64_REDUCE 0x1   /* residual/objective reductions and the stopping test in FP64 (else FP32) */
+#define SR3D_FP64_REDUCE 0x1   /* residual/objective reductions and the stopping test in FP64 (else FP32);
+                                  per-voxel terms are FP32 and each thread first sums its
+                                  own (at most 64 per stencil thread) in FP32 */
 #define SR3D_RESUME      0x2   /* start from problem.state (must be non-NULL) */
 #define SR3D_USE_GRAPH   0x4   /* replay captured iterations as a HIP graph */
 #define SR3D_PROFILE     0x8   /* time every kernel launch with HIP events on the caller's

@@ -47,14 +47,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// Isotropic shrink (Algorithm 1 step 5b): u = a max(|a| - thr, 0) / |a|,
+// written as a max(1 - thr / |a|, 0) with the hardware reciprocal square
+// root; a = 0 gives u = 0.
 __device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr, float &u0,
                                         float &u1, float &u2) {
   const float n2 = a0 * a0 + a1 * a1 + a2 * a2;
-  float s = 0.f;
-  if (n2 > 0.f) {
-    const float n = sqrtf(n2);
-    s = fmaxf(n - thr, 0.f) / n;
-  }
+  const float s = n2 > 0.f ? fmaxf(1.f - thr * __builtin_amdgcn_rsqf(n2), 0.f) : 0.f;
   u0 = a0 * s;
   u1 = a1 * s;
   u2 = a2 * s;
@@ -187,7 +186,9 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
     }
   };
 
-  Acc acc[6] = {0, 0, 0, 0, 0, 0};
+  // Each thread sums its own points (at most 2 per plane over <= 32 planes)
+  // in FP32; the sums across threads, workgroups and the volume are in Acc.
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float pw[2], pd[2], pu[2];  // s-components at the previous plane
   float xr[XR_PT];
   float nuc[3][3], nun[3][3];
@@ -248,12 +249,12 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
         a.nu_out[v + NT] = q.nn[1];
         a.nu_out[v + 2 * NT] = q.nn[2];
         if (STATS) {
-          const Acc l2 = (Acc)q.l[0] * q.l[0] + (Acc)q.l[1] * q.l[1] + (Acc)q.l[2] * q.l[2];
+          const float l2 = q.l[0] * q.l[0] + q.l[1] * q.l[1] + q.l[2] * q.l[2];
           const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
-          acc[0] += (Acc)r0 * r0 + (Acc)r1 * r1 + (Acc)r2 * r2;
+          acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
           acc[1] += l2;
-          acc[2] += (Acc)q.u[0] * q.u[0] + (Acc)q.u[1] * q.u[1] + (Acc)q.u[2] * q.u[2];
-          acc[3] += sqrt(l2);
+          acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+          acc[3] += l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;  // |(L x)_j|
         }
       }
     }
@@ -280,8 +281,8 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
       if (pval[k]) {
         a.theta[sb + poff[k]] = ltw;
         if (STATS) {
-          acc[4] += (Acc)ltu * ltu;
-          acc[5] += (Acc)ltd * ltd;
+          acc[4] += ltu * ltu;
+          acc[5] += ltd * ltd;
         }
       }
       pw[k] = cw[k];
@@ -294,10 +295,13 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
       for (int c = 0; c < 3; ++c) nuc[k][c] = nun[k][c];
   }
   if (STATS) {
-    block_reduce_n<Acc>(acc, 6, sh);
+    Acc acc_t[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc_t[q] = (Acc)acc[q];
+    block_reduce_n<Acc>(acc_t, 6, sh);
     if (tid == 0) {
       Acc *p = reinterpret_cast<Acc *>(a.part);
-      for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + slot] = acc[q];
+      for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + slot] = acc_t[q];
     }
   }
 }
