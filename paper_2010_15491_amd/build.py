@@ -22,7 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsr3d.so")
 
-SOURCES = ["fft.hip", "fft_m.hip", "fft_strided.hip", "fold.hip", "solve_s.hip", "stencil.hip", "cnn.hip",
+SOURCES = ["solve_s_i0.hip", "solve_s_i1.hip", "solve_s_i2.hip", "solve_s_i3.hip", "fft.hip",
+           "fft_m.hip", "fft_strided.hip", "fold.hip", "solve_s.hip", "stencil.hip", "cnn.hip",
            "api.hip"]
 
 ARCH = "gfx950"

@@ -364,7 +364,7 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
     if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st)))
       return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -558,7 +558,8 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
   }
   for (int v = 0; v < n; ++v) {
     if (fused[v]) {
-      auto &gr = group(8, g[v].S, g[v].sp.dm);
+      // variant: member bound, +1 for the instance with the group size fixed
+      auto &gr = group(8, g[v].S, 2 * g[v].sp.dm + (g[v].D == g[v].sp.dm ? 1 : 0));
       for (int t = 0; t < g[v].sp.units; ++t) gr.items.push_back(make_int2(v, t));
       continue;
     }
@@ -650,7 +651,9 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
   for (auto &gr : plan.groups) {
     if (gr.kind != 8) continue;
     prof_begin(kStSolveS, st);
-    e = solve_s(gr.key, gr.variant, H.solve, items_of(gr), (int)gr.items.size(), fp64, st);
+    const int dm = gr.variant / 2;
+    e = solve_s(gr.key, dm, (gr.variant & 1) ? dm : -1, H.solve, items_of(gr),
+                (int)gr.items.size(), fp64, st);
     prof_end(st);
     if (e) return e;
   }

@@ -16,32 +16,12 @@
 // {j_m, -j_m mod M_l}, and, when the class is self-conjugate, the pair member
 // with the smaller (j_s, j_n) index. The solved group writes X_k for its
 // stored members and conj(X_k) at the stored -k of the partner group. The
-// pointwise arithmetic is that of the unfused fold kernel (leave-one-out
-// Woodbury in FP32, exact FP64 elimination of the zero-frequency group).
-#include "fft_core.h"
+// pointwise formulas are those of the unfused fold kernel (leave-one-out
+// Woodbury in FP32, here with hardware reciprocals; exact FP64 elimination of
+// the zero-frequency group). Kernel instances live in solve_s_i*.hip.
+#include "solve_s_core.h"
 
 namespace sr3d {
-
-// Lines per workgroup: as many as fit two workgroups in a CU's 160 KB of LDS
-// (lines, twiddles, |sigma_s|^2 table and side tables), at most 64.
-constexpr int solve_tile(int S) {
-  const int t = (81920 - 12 * S - 2048) / (8 * S);
-  return t > 64 ? 64 : t;
-}
-
-#define SR3D_SOLVE_S_LENGTHS(X) \
-  X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
-
-static bool solve_s_len(int S) {
-  switch (S) {
-#define SR3D_CASE(L) case L:
-    SR3D_SOLVE_S_LENGTHS(SR3D_CASE)
-#undef SR3D_CASE
-    return true;
-    default:
-      return false;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Host plan
@@ -137,86 +117,6 @@ SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds) {
   return P;
 }
 
-// ---------------------------------------------------------------------------
-// Device
-// ---------------------------------------------------------------------------
-
-// Global-memory views of pointers read from a descriptor in memory (the
-// compiler cannot infer their address space and would emit flat accesses,
-// which share the LDS wait counter).
-typedef __attribute__((address_space(1))) const float cgfloat;
-typedef __attribute__((address_space(1))) const int cgint;
-typedef __attribute__((address_space(1))) const uint64_t cgu64;
-typedef __attribute__((address_space(1))) uint64_t gu64;
-
-__device__ __forceinline__ float2 u64_f2(uint64_t v) {
-  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
-}
-__device__ __forceinline__ uint64_t f2_u64(float2 v) {
-  return (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
-}
-// complex value at byte offset `off` from global base `b`
-__device__ __forceinline__ float2 gld2(const void *b, uint32_t off) {
-  return u64_f2(*(cgu64 *)((__attribute__((address_space(1))) const char *)b + off));
-}
-__device__ __forceinline__ void gst2(void *b, uint32_t off, float2 v) {
-  *(gu64 *)((__attribute__((address_space(1))) char *)b + off) = f2_u64(v);
-}
-
-__device__ __forceinline__ float2 s_mul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 s_conj(float2 a) { return make_float2(a.x, -a.y); }
-
-template <typename T>
-__device__ __forceinline__ T unit_sum(T v, T *sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  T r = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-  return r;
-}
-
-__device__ __forceinline__ int solve_xcd_unit(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int x = b & 7, l = b >> 3;
-  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
-
-// Group of slot `slot` of a unit whose m-block has nc classes (slots
-// 0 .. 2 S_l nc - 1): returns false for an empty or skipped slot.
-struct SlotGroup {
-  int js, jn, jm, ji, ci;
-  bool selfc;
-};
-__device__ __forceinline__ int block_classes(const int *mj, int CB) {
-  int nc = 0;
-  while (nc < CB && mj[nc] >= 0) ++nc;
-  return nc;
-}
-__device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, int nc, int j0,
-                                           int j1, int slot, SlotGroup &g) {
-  const int ci = slot % nc, r1 = slot / nc;
-  const int ji = r1 & 1, js = r1 >> 1;
-  const int jm = mj[ci];
-  if (jm < 0 || (ji && j1 < 0)) return false;
-  const int jn = ji ? j1 : j0;
-  bool selfc = false;
-  if (jm == 0 || 2 * jm == a.Ml) {  // self-conjugate m class: keep one of j, -j
-    const int jsn = js == 0 ? 0 : a.Sl - js, jnn = jn == 0 ? 0 : a.Nl - jn;
-    const long lin = (long)js * a.Nl + jn, lnn = (long)jsn * a.Nl + jnn;
-    if (lin > lnn) return false;
-    selfc = lin == lnn;
-  }
-  g = SlotGroup{js, jn, jm, ji, ci, selfc};
-  return true;
-}
-
 // Setup: Lambda of every member (conjugated where the member is a mirror) and
 // the LR spectrum Y_j of every solved group, in (unit, member, slot) order.
 __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
@@ -265,331 +165,14 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
   }
 }
 
-// LDS side tables of a unit (sizes bound the plan: lines <= 64, classes per
-// block * dr <= 64, rows <= 2 dc <= 64).
-struct UnitTabs {
-  int loff[64];     // global offset of line l within an s-plane, or -1
-  int mj[64];       // class representatives j_m of the m-block (-1: none)
-  int nc;           // classes in the m-block
-  int mpos[64];     // (ci, a): line position of the stored rep of k_m, bit 30 = mirrored
-  float gmv[64];    // (ci, a): |sigma_m(k_m)|^2
-  int rowd[64];     // (ji, b): row of k_n
-  int rowm[64];     // (ji, b): row of -k_n
-  float gnv[64];    // (ji, b): |sigma_n(k_n)|^2
-};
-
-template <int S, int DM, typename Acc>
-__device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
-                                             const float2 *__restrict__ tw, float2 *lds,
-                                             float2 *stw, float *sgs, UnitTabs &ut, Acc *red) {
-  constexpr int T = solve_tile(S), TP = T;
-  const int gn = u / a.NB, bm = u - gn * a.NB;
-  cgint *tab = (cgint *)a.tab;
-  cgfloat *gmt = (cgfloat *)a.gm, *gnt = (cgfloat *)a.gn, *gst = (cgfloat *)a.gs;
-  const int p0 = tab[a.o_p0 + bm], cnt = tab[a.o_cnt + bm];
-  const int j0 = tab[a.o_nj + 2 * gn], j1 = tab[a.o_nj + 2 * gn + 1];
-  const int nji = j1 < 0 ? 1 : 2;
-  const int nlines = nji * a.dc * cnt;
-  const long plane = (long)a.N * a.P;
-  stage_twiddles<S>(stw, tw);
-  for (int i = threadIdx.x; i < S; i += kThreads) sgs[i] = gst[i];
-  {
-    const int t = threadIdx.x;
-    if (t < T) {
-      int off = -1;
-      if (t < nlines) {
-        const int row = t / cnt, pp = t - row * cnt;
-        const int ji = row / a.dc, b = row - ji * a.dc;
-        off = ((ji ? j1 : j0) + b * a.Nl) * a.P + p0 + pp;
-      }
-      ut.loff[t] = off;
-    }
-    if (t < a.CB) ut.mj[t] = tab[a.o_mj + bm * a.CB + t];
-    if (t == 0) {
-      int nc = 0;
-      while (nc < a.CB && tab[a.o_mj + bm * a.CB + nc] >= 0) ++nc;
-      ut.nc = nc;
-    }
-    if (t < a.CB * a.dr) {
-      const int ci = t / a.dr, ia = t - ci * a.dr;
-      const int jm = tab[a.o_mj + bm * a.CB + ci];
-      if (jm >= 0) {
-        const int km = jm + ia * a.Ml;
-        const bool direct = km < a.Mh;
-        const int rm = direct ? km : a.M - km;
-        ut.mpos[t] = (tab[a.Mh + rm] - p0) | (direct ? 0 : (1 << 30));
-        ut.gmv[t] = gmt[km];
-      }
-    }
-    if (t < nji * a.dc) {
-      const int ji = t / a.dc, b = t - ji * a.dc;
-      const int jn = ji ? j1 : j0;
-      const int jnn = jn == 0 ? 0 : a.Nl - jn;
-      const int jim = (jnn == j0) ? 0 : 1;
-      const int bmir = (jn == 0) ? ((a.dc - b) % a.dc) : (a.dc - 1 - b);
-      ut.rowd[t] = t;
-      ut.rowm[t] = jim * a.dc + bmir;
-      ut.gnv[t] = gnt[jn + b * a.Nl];
-    }
-  }
-  __syncthreads();
-  // Element w of the tile is (s, line) = (w / T, w % T), at lds[w]. All of a
-  // thread's loads are issued before the first LDS store; lines past the
-  // unit's load element 0 and are zeroed.
-  constexpr int NE = (S * T + kThreads - 1) / kThreads;
-  constexpr int NH = (NE + 1) / 2;  // loads in flight per thread: half the tile
-  const uint32_t pl = (uint32_t)plane;
-#pragma unroll
-  for (int h = 0; h < NE; h += NH) {
-    float2 v[NH];
-#pragma unroll
-    for (int k = 0; k < NH; ++k) {
-      const int w = threadIdx.x + (h + k) * kThreads;
-      const int s = w / T, line = w - s * T;
-      const int off = (h + k < NE && w < S * T) ? ut.loff[line] : -1;
-      const float2 x = gld2(a.W, ((uint32_t)(off >= 0 ? s : 0) * pl + (uint32_t)(off >= 0 ? off : 0)) * 8u);
-      v[k] = off >= 0 ? x : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int k = 0; k < NH; ++k) {
-      const int w = threadIdx.x + (h + k) * kThreads;
-      if (h + k < NE && w < S * T) lds[w] = v[k];
-    }
-  }
-  __syncthreads();
-  fft_passes<S, T, TP, 0, 1>(lds, stw);
-
-  // Solve. Every LDS entry is read and written by one thread only.
-  const float fd = (float)a.D;
-  const Acc inv_d = (Acc)1 / (Acc)a.D;
-  Acc resid = 0;
-  // Lambda of member q of slot i at Lu[q * gmax + i]; Y of slot i at Yu[i]
-  cgu64 *Lu = (cgu64 *)a.Lg + (long)u * a.D * a.gmax;
-  cgu64 *Yu = (cgu64 *)a.Yg + (long)u * a.gmax;
-  // Lambda and Y of the next slot are loaded while the current one is solved.
-  float2 lnext[DM], ynext = make_float2(0.f, 0.f);
-  const int nc = ut.nc, gcount = a.Sl * 2 * nc;  // slots of this unit
-  if ((int)threadIdx.x < gcount) {
-    ynext = u64_f2(Yu[threadIdx.x]);
-#pragma unroll
-    for (int q = 0; q < DM; ++q)
-      if (q < a.D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + threadIdx.x]);
-  }
-  for (int slot = threadIdx.x; slot < gcount; slot += kThreads) {
-    float2 lcur[DM];
-#pragma unroll
-    for (int q = 0; q < DM; ++q) lcur[q] = lnext[q];
-    const float2 Yj = ynext;
-    const int nslot = slot + kThreads;
-    if (nslot < gcount) {
-      ynext = u64_f2(Yu[nslot]);
-#pragma unroll
-      for (int q = 0; q < DM; ++q)
-        if (q < a.D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
-    }
-    SlotGroup g;
-    if (!slot_group(a, ut.mj, nc, j0, j1, slot, g)) continue;
-    // Members: Lambda, B = conj(Lambda) Y + mu W, A = mu G, the LDS index of
-    // the stored entry (li >= 0: the member itself, else -1-index of its
-    // mirror) and, for a stored member whose -k is stored as well and belongs
-    // to the partner group, the LDS index of -k (mi, else -1).
-    float2 B[DM];
-    float A[DM];
-    int li[DM], mi[DM];
-    int ia = 0, ib = 0, ic = 0;
-#pragma unroll
-    for (int q = 0; q < DM; ++q) {
-      if (q < a.D) {
-        const int ks = g.js + ic * a.Sl;
-        const int mp = ut.mpos[g.ci * a.dr + ia];
-        const bool direct = (mp & (1 << 30)) == 0;
-        const int nrow = g.ji * a.dc + ib;
-        const int rs = ks == 0 ? 0 : S - ks;
-        const int mirror = rs * TP + ut.rowm[nrow] * cnt + (mp & ~(1 << 30));
-        const int idx = direct ? ks * TP + ut.rowd[nrow] * cnt + mp : mirror;
-        float2 w = lds[idx];
-        if (!direct) w.y = -w.y;
-        const float2 l = lcur[q];
-        const float Aq = a.mu * (sgs[ks] + ut.gnv[nrow] + ut.gmv[g.ci * a.dr + ia]);
-        const float2 cb = s_mul(s_conj(l), Yj);
-        B[q] = make_float2(cb.x + a.mu * w.x, cb.y + a.mu * w.y);
-        A[q] = Aq;
-        li[q] = direct ? idx : -1 - idx;
-        const int km = g.jm + ia * a.Ml;
-        mi[q] = (direct && !g.selfc && (km == 0 || 2 * km == a.M)) ? mirror : -1;
-        if (++ia == a.dr) {
-          ia = 0;
-          if (++ib == a.dc) {
-            ib = 0;
-            ++ic;
-          }
-        }
-      }
-    }
-    // Store X_q (scaled, conjugated for the inverse pass) and add L_q X_q to
-    // the data-residual sum.
-    float2 acc = make_float2(0.f, 0.f);
-    auto emit = [&](int q, float2 x) {
-      const float2 xs = make_float2(x.x * a.scale, x.y * a.scale);
-      if (li[q] >= 0) {
-        lds[li[q]] = make_float2(xs.x, -xs.y);
-        if (mi[q] >= 0) lds[mi[q]] = xs;
-      } else if (!g.selfc) {
-        lds[-1 - li[q]] = xs;
-      }
-      const float2 lx = s_mul(lcur[q], x);
-      acc.x += lx.x;
-      acc.y += lx.y;
-    };
-    if (g.js == 0 && g.jn == 0 && g.jm == 0) {
-      // Zero-frequency group: member 0 is k = 0 with A = 0. Exact elimination
-      // of (1/d) conj(L) L^T X + diag(A) X = B, in FP64.
-      const double l0r = lcur[0].x, l0i = lcur[0].y;
-      const double l0n = l0r * l0r + l0i * l0i;
-      if (l0n == 0.0) {
-        a.ctrl->status = SR3D_ERR_SINGULAR;
-        a.ctrl->done = 1;
-#pragma unroll
-        for (int q = 0; q < DM; ++q)
-          if (q < a.D) emit(q, make_float2(0.f, 0.f));
-      } else {
-        const double br = B[0].x, bi = B[0].y;
-        const double sr = (double)a.D * (br * l0r - bi * l0i) / l0n;
-        const double si = (double)a.D * (br * l0i + bi * l0r) / l0n;
-        double accr = 0.0, acci = 0.0;
-#pragma unroll
-        for (int q = 1; q < DM; ++q) {
-          if (q < a.D) {
-            const double lr = lcur[q].x, lq = lcur[q].y;
-            const double tr = (lr * sr + lq * si) / (double)a.D;
-            const double ti = (lr * si - lq * sr) / (double)a.D;
-            const double xr = ((double)B[q].x - tr) / (double)A[q];
-            const double xi = ((double)B[q].y - ti) / (double)A[q];
-            emit(q, make_float2((float)xr, (float)xi));
-            accr += lr * xr - lq * xi;
-            acci += lr * xi + lq * xr;
-          }
-        }
-        const double nr = sr - accr, ni = si - acci;
-        emit(0, make_float2((float)((nr * l0r + ni * l0i) / l0n),
-                            (float)((ni * l0r - nr * l0i) / l0n)));
-      }
-    } else {
-      // Leave-one-out Woodbury solve in FP32 (the unfused fold kernel's
-      // formula; reciprocals from the hardware rcp):
-      //   X_a = [B_a (d + S_a^(-a)) - conj(L_a) S_b^(-a)] / [A_a (d + S_a)].
-      float preP[DM];
-      float2 preQ[DM];
-      float sp = 0.f;
-      float2 sq = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int q = 0; q < DM; ++q) {
-        if (q < a.D) {
-          const float inv = __builtin_amdgcn_rcpf(A[q]);
-          const float2 l = lcur[q];
-          const float2 lb = s_mul(l, B[q]);
-          preP[q] = sp;
-          preQ[q] = sq;
-          sp += (l.x * l.x + l.y * l.y) * inv;
-          sq.x += lb.x * inv;
-          sq.y += lb.y * inv;
-        }
-      }
-      const float rS = __builtin_amdgcn_rcpf(fd + sp);
-      float suP = 0.f;
-      float2 suQ = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int q = DM - 1; q >= 0; --q) {
-        if (q < a.D) {
-          const float2 l = lcur[q];
-          const float saL = preP[q] + suP;
-          const float2 sbL = make_float2(preQ[q].x + suQ.x, preQ[q].y + suQ.y);
-          const float2 t = s_mul(s_conj(l), sbL);
-          const float nd = fd + saL;
-          const float inv = __builtin_amdgcn_rcpf(A[q]);
-          const float rden = inv * rS;
-          emit(q, make_float2((B[q].x * nd - t.x) * rden, (B[q].y * nd - t.y) * rden));
-          const float2 lb = s_mul(l, B[q]);
-          suP += (l.x * l.x + l.y * l.y) * inv;
-          suQ.x += lb.x * inv;
-          suQ.y += lb.y * inv;
-        }
-      }
-    }
-    // Data residual of the new x at j (and, for a pair, at -j).
-    if (a.partial) {
-      const Acc rr = (Acc)Yj.x - (Acc)acc.x * inv_d;
-      const Acc ri = (Acc)Yj.y - (Acc)acc.y * inv_d;
-      resid += (g.selfc ? (Acc)1 : (Acc)2) * (rr * rr + ri * ri);
-    }
-  }
-  __syncthreads();
-  fft_passes<S, T, TP, 0, 1>(lds, stw);
-  // The tile indices are recomputed here rather than kept live from the load
-  // phase (an empty asm hides that this is the same thread index).
-  int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));
-#pragma unroll
-  for (int k = 0; k < NE; ++k) {
-    const int w = tid + k * kThreads;
-    const int s = w / T, line = w - s * T;
-    const int off = (w < S * T) ? ut.loff[line] : -1;
-    if (off >= 0) {
-      const float2 v = lds[w];
-      gst2(a.W, ((uint32_t)s * pl + (uint32_t)off) * 8u, make_float2(v.x, -v.y));
-    }
-  }
-  if (a.partial) {
-    const Acc sum = unit_sum<Acc>(resid, red);
-    if (threadIdx.x == 0) reinterpret_cast<Acc *>(a.partial)[u] = sum;
-  }
-}
-
-// Two workgroups per CU (the LDS tile allows two) for the 8-member instances.
-template <int S, int DM, typename Acc>
-__global__ __launch_bounds__(kThreads, (DM <= 8 ? 2 : 1)) void k_solve_s(const SolveSArgs *__restrict__ descs,
-                                                      const int2 *__restrict__ items,
-                                                      const float2 *__restrict__ tw) {
-  int v = 0, u;
-  if (items) {
-    const int2 it = items[blockIdx.x];
-    v = it.x;
-    u = it.y;
-  } else {
-    u = solve_xcd_unit(blockIdx.x, descs[0].units);
-  }
-  const SolveSArgs a = descs[v];
-  if (a.done && *a.done) return;
-  constexpr int T = solve_tile(S);
-  __shared__ float2 lds[S * T];
-  __shared__ float2 stw[S];
-  __shared__ float sgs[S];
-  __shared__ UnitTabs ut;
-  __shared__ Acc red[kThreads / 64];
-  solve_s_body<S, DM, Acc>(a, u, tw, lds, stw, sgs, ut, red);
-}
-
-template <int S, typename Acc>
-static void launch_solve_s_t(int dm, const SolveSArgs *descs, const int2 *items, int nwg,
-                             hipStream_t st) {
-  const float2 *tw = twiddles(S);
-  if (dm <= 8)
-    hipLaunchKernelGGL((k_solve_s<S, 8, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs, items, tw);
-  else if (dm <= 16)
-    hipLaunchKernelGGL((k_solve_s<S, 16, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs, items, tw);
-  else
-    hipLaunchKernelGGL((k_solve_s<S, 32, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs, items, tw);
-}
-
-hipError_t solve_s(int S, int dm, const SolveSArgs *descs, const int2 *items, int nwg, bool fp64,
-                   hipStream_t st) {
+hipError_t solve_s(int S, int dm, int d, const SolveSArgs *descs, const int2 *items, int nwg,
+                   bool fp64, hipStream_t st) {
   if (nwg == 0) return hipSuccess;
   if (!twiddles(S)) return hipErrorInvalidValue;
   switch (S) {
-#define SR3D_CASE(L)                                                         \
-  case L:                                                                    \
-    if (fp64) launch_solve_s_t<L, double>(dm, descs, items, nwg, st);        \
-    else launch_solve_s_t<L, float>(dm, descs, items, nwg, st);              \
+#define SR3D_CASE(L)                                        \
+  case L:                                                   \
+    solve_s_launch_##L(dm, d, descs, items, nwg, fp64, st); \
     break;
     SR3D_SOLVE_S_LENGTHS(SR3D_CASE)
 #undef SR3D_CASE
