@@ -24,6 +24,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -163,11 +164,11 @@ def main():
     flags_all = flags
     # FFT tile variants: timed once on this device, outside the timed steps.
     sr3d.autotune([(hr, wl["rate"])])
-    tune_path = os.path.join(ROOT, "gpurun_out", "fft_tiles.txt")
-    os.makedirs(os.path.dirname(tune_path), exist_ok=True)
-    sr3d.tune_save(tune_path)
-    with open(tune_path) as f:
-        fft_tiles = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
+    with tempfile.TemporaryDirectory() as td:
+        tune_path = os.path.join(td, "fft_tiles.txt")
+        sr3d.tune_save(tune_path)
+        with open(tune_path) as f:
+            fft_tiles = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
 
     def step(fl=None):
         return sr3d.tv_admm(y, psf, wl["rate"], wl["lam"], wl["mu"], wl["max_iter"],

@@ -10,7 +10,7 @@ blocking, fusion or reordering beyond what the cited formula states; library
 primitives used as steps are scipy.fft (unnormalised 3D DFT) and
 numpy.linalg.solve.
 
-Conventions (readings of the paper, each listed in the design doc):
+Conventions (readings of the paper where it is silent, ambiguous or garbled):
   * A volume of size m x n x s (m = rows, fastest in the lexicographic order of
     Sec. II-A and the Kronecker order of eq. (8)) is a C-order array of shape
     (s, n, m).

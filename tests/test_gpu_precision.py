@@ -5,8 +5,8 @@ sigma = (1.2, 1.2, 2.0), against the FP64 oracle.
 
 By default the GPU and the oracle run 2 iterations (the oracle takes a few
 seconds per iteration at this size). With SR3D_PRECISION_ITERS=100 the study
-runs the full 100 iterations and writes its report to
-gpurun_out/precision_512x512x256.json.
+runs the full 100 iterations; with SR3D_REPORT_DIR set it also writes its
+report there as precision_512x512x256.json.
 """
 
 import json
@@ -68,9 +68,10 @@ def test_precision_study_512x512x256():
         r["objective_err"] = abs(r["objective"] - obj_ref) / abs(obj_ref)
         report[name] = r
     print(json.dumps(report))
-    if iters >= 100:
-        os.makedirs("gpurun_out", exist_ok=True)
-        with open(os.path.join("gpurun_out", "precision_512x512x256.json"), "w") as f:
+    out_dir = os.environ.get("SR3D_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "precision_512x512x256.json"), "w") as f:
             json.dump(report, f, indent=1)
     assert err < 1e-5
     assert res["fp64_reduce"]["objective_err"] < 1e-6
