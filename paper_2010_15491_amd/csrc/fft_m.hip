@@ -15,11 +15,12 @@ template <int M, int E>
 __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
                                               const float2 *__restrict__ twh,
                                               const float2 *__restrict__ twm, float2 *lds,
-                                              float2 *stw, int *sperm) {
+                                              float2 *stw, int *sperm, float2 *stwm) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
   const long row0 = (long)bid * T;
   const long nrows = d.nrows;
   stage_twiddles<H>(stw, twh);
+  for (int i = threadIdx.x; i < MH; i += kThreads) stwm[i] = twm[i];
   const bool perm = d.kofp != nullptr;
   const long pitch = d.pitch ? d.pitch : MH;
   if (perm)
@@ -43,7 +44,7 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
       // E = (Z[k] + conj Z[H-k]) / 2 ; O = -i (Z[k] - conj Z[H-k]) / 2
       const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      const float2 wo = cmul(twm[k], o);
+      const float2 wo = cmul(stwm[k], o);
       out[r * pitch + p] = make_float2(e.x + wo.x, e.y + wo.y);
     }
   }
@@ -53,7 +54,7 @@ template <int M, int E>
 __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
                                               const float2 *__restrict__ twh,
                                               const float2 *__restrict__ twm, float2 *lds,
-                                              float2 *stw, int *sperm) {
+                                              float2 *stw, int *sperm, float2 *stwm) {
   constexpr int H = M / 2, T = tile_lines(H, E), TP = T + 1, MH = M / 2 + 1;
   const long row0 = (long)bid * T;
   const long nrows = d.nrows;
@@ -61,10 +62,10 @@ __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
   stage_twiddles<H>(stw, twh);
   const bool perm = d.posk != nullptr;
   const long pitch = d.pitch ? d.pitch : MH;
-  if (perm) {
+  for (int i = threadIdx.x; i < H; i += kThreads) stwm[i] = twm[i];
+  if (perm)
     for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.posk[i];
-    __syncthreads();
-  }
+  __syncthreads();
   for (int w = threadIdx.x; w < H * T; w += kThreads) {
     const int k = w % H, t = w / H;
     const long r = row0 + t;
@@ -75,7 +76,7 @@ __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
       // E = (X[k] + conj X[H-k]) / 2 ; O = e^{+2 pi i k/M} (X[k] - conj X[H-k]) / 2
       const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
       const float2 dd = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
-      const float2 wk = twm[k];
+      const float2 wk = stwm[k];
       const float2 o = cmul(make_float2(wk.x, -wk.y), dd);
       // Z = E + i O, stored conjugated (inverse through the forward passes)
       v = make_float2(e.x - o.y, -(e.y + o.x));
@@ -161,8 +162,9 @@ __device__ __forceinline__ void row_body(const RowDesc &d, int bid, const float2
     __shared__ float2 lds[H * TP];
     __shared__ float2 stw[H];
     __shared__ int sperm[M / 2 + 1];
-    if (C2R) c2r_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm);
-    else r2c_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm);
+    __shared__ float2 stwm[M / 2 + 1];
+    if (C2R) c2r_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm, stwm);
+    else r2c_half_body<M, E>(d, bid, twh, twm, lds, stw, sperm, stwm);
   } else {
     constexpr int T = tile_lines(M, E), TP = T + 1;
     __shared__ float2 lds[M * TP];

@@ -194,7 +194,6 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   // the member loops unroll into straight-line code.
   const int D = EXACT ? DM : a.D;
   const float fd = (float)D;
-  const Acc inv_d = (Acc)1 / (Acc)D;
   Acc resid = 0;
   // Lambda of member q of slot i at Lu[q * gmax + i]; Y of slot i at Yu[i]
   cgu64 *Lu = (cgu64 *)a.Lg + (long)u * D * a.gmax;
@@ -259,21 +258,17 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
         }
       }
     }
-    // Store X_q (scaled, conjugated for the inverse pass) and add L_q X_q to
-    // the data-residual sum.
-    float2 acc = make_float2(0.f, 0.f);
-    auto emit = [&](int q, float2 x) {
-      const float2 xs = make_float2(x.x * a.scale, x.y * a.scale);
+    // Store X_q (already scaled by 1/N_h), conjugated for the inverse pass,
+    // at the stored member, and conj at the partner's stored -k.
+    auto emit = [&](int q, float2 xs) {
       if (li[q] >= 0) {
         lds[li[q]] = make_float2(xs.x, -xs.y);
         if (mi[q] >= 0) lds[mi[q]] = xs;
       } else if (!g.selfc) {
         lds[-1 - li[q]] = xs;
       }
-      const float2 lx = s_mul(lcur[q], x);
-      acc.x += lx.x;
-      acc.y += lx.y;
     };
+    float2 mean;  // (1/d) sum_b L_b X_b of the new x, for the data residual
     if (g.js == 0 && g.jn == 0 && g.jm == 0) {
       // Zero-frequency group: member 0 is k = 0 with A = 0. Exact elimination
       // of (1/d) conj(L) L^T X + diag(A) X = B, in FP64.
@@ -285,8 +280,10 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
 #pragma unroll
         for (int q = 0; q < DM; ++q)
           if (q < D) emit(q, make_float2(0.f, 0.f));
+        mean = make_float2(0.f, 0.f);
       } else {
         const double br = B[0].x, bi = B[0].y;
+        // s = sum_b L_b X_b = d B_0 / conj(L_0)
         const double sr = (double)D * (br * l0r - bi * l0i) / l0n;
         const double si = (double)D * (br * l0i + bi * l0r) / l0n;
         double accr = 0.0, acci = 0.0;
@@ -298,37 +295,43 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
             const double ti = (lr * si - lq * sr) / (double)D;
             const double xr = ((double)B[q].x - tr) / (double)A[q];
             const double xi = ((double)B[q].y - ti) / (double)A[q];
-            emit(q, make_float2((float)xr, (float)xi));
+            emit(q, make_float2((float)xr * a.scale, (float)xi * a.scale));
             accr += lr * xr - lq * xi;
             acci += lr * xi + lq * xr;
           }
         }
         const double nr = sr - accr, ni = si - acci;
-        emit(0, make_float2((float)((nr * l0r + ni * l0i) / l0n),
-                            (float)((ni * l0r - nr * l0i) / l0n)));
+        emit(0, make_float2((float)((nr * l0r + ni * l0i) / l0n) * a.scale,
+                            (float)((ni * l0r - nr * l0i) / l0n) * a.scale));
+        mean = make_float2((float)(sr / (double)D), (float)(si / (double)D));
       }
     } else {
       // Leave-one-out Woodbury solve in FP32 (the unfused fold kernel's
-      // formula; reciprocals from the hardware rcp):
-      //   X_a = [B_a (d + S_a^(-a)) - conj(L_a) S_b^(-a)] / [A_a (d + S_a)].
-      float preP[DM];
-      float2 preQ[DM];
+      // formula, with hardware reciprocals):
+      //   X_a = [B_a (d + S_a^(-a)) - conj(L_a) S_b^(-a)] / [A_a (d + S_a)],
+      //   S_a = sum_b |L_b|^2 / A_b,  S_b = sum_b L_b B_b / A_b.
+      // The group's mean (1/d) sum_b L_b X_b equals S_b / (d + S_a).
+      float inv[DM], pt[DM], preP[DM];
+      float2 qt[DM], preQ[DM];
       float sp = 0.f;
       float2 sq = make_float2(0.f, 0.f);
 #pragma unroll
       for (int q = 0; q < DM; ++q) {
         if (q < D) {
-          const float inv = __builtin_amdgcn_rcpf(A[q]);
+          inv[q] = __builtin_amdgcn_rcpf(A[q]);
           const float2 l = lcur[q];
           const float2 lb = s_mul(l, B[q]);
+          pt[q] = (l.x * l.x + l.y * l.y) * inv[q];
+          qt[q] = make_float2(lb.x * inv[q], lb.y * inv[q]);
           preP[q] = sp;
           preQ[q] = sq;
-          sp += (l.x * l.x + l.y * l.y) * inv;
-          sq.x += lb.x * inv;
-          sq.y += lb.y * inv;
+          sp += pt[q];
+          sq.x += qt[q].x;
+          sq.y += qt[q].y;
         }
       }
       const float rS = __builtin_amdgcn_rcpf(fd + sp);
+      const float rSs = rS * a.scale;
       float suP = 0.f;
       float2 suQ = make_float2(0.f, 0.f);
 #pragma unroll
@@ -339,20 +342,19 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
           const float2 sbL = make_float2(preQ[q].x + suQ.x, preQ[q].y + suQ.y);
           const float2 t = s_mul(s_conj(l), sbL);
           const float nd = fd + saL;
-          const float inv = __builtin_amdgcn_rcpf(A[q]);
-          const float rden = inv * rS;
+          const float rden = inv[q] * rSs;
           emit(q, make_float2((B[q].x * nd - t.x) * rden, (B[q].y * nd - t.y) * rden));
-          const float2 lb = s_mul(l, B[q]);
-          suP += (l.x * l.x + l.y * l.y) * inv;
-          suQ.x += lb.x * inv;
-          suQ.y += lb.y * inv;
+          suP += pt[q];
+          suQ.x += qt[q].x;
+          suQ.y += qt[q].y;
         }
       }
+      mean = make_float2(sq.x * rS, sq.y * rS);
     }
     // Data residual of the new x at j (and, for a pair, at -j).
     if (a.partial) {
-      const Acc rr = (Acc)Yj.x - (Acc)acc.x * inv_d;
-      const Acc ri = (Acc)Yj.y - (Acc)acc.y * inv_d;
+      const Acc rr = (Acc)Yj.x - (Acc)mean.x;
+      const Acc ri = (Acc)Yj.y - (Acc)mean.y;
       resid += (g.selfc ? (Acc)1 : (Acc)2) * (rr * rr + ri * ri);
     }
   }

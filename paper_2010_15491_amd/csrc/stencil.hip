@@ -417,17 +417,17 @@ hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, flo
 
 // Sums of the 6 stencil partial arrays and the fold partials, all loads of a
 // thread issued before any shuffle.
-template <typename Acc>
+template <typename Acc, int NT>
 __device__ __forceinline__ void reduce_body(Ctrl *c, const Acc *ps, int nbs, const Acc *pf,
                                             int nbf) {
-  __shared__ Acc sh[7][16];
+  __shared__ Acc sh[7][NT / 64];
   Acc q[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < nbs; i += 1024) {
+  for (int i = threadIdx.x; i < nbs; i += NT) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) q[k] += ps[(long)k * nbs + i];
   }
   if (pf)
-    for (int i = threadIdx.x; i < nbf; i += 1024) q[6] += pf[i];
+    for (int i = threadIdx.x; i < nbf; i += NT) q[6] += pf[i];
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
 #pragma unroll
@@ -440,7 +440,7 @@ __device__ __forceinline__ void reduce_body(Ctrl *c, const Acc *ps, int nbs, con
   if (threadIdx.x != 0) return;
   for (int k = 0; k < 7; ++k) {
     Acc t = 0;
-    for (int w = 0; w < 16; ++w) t += sh[k][w];
+    for (int w = 0; w < NT / 64; ++w) t += sh[k][w];
     q[k] = t;
   }
   bool finite = true;
@@ -473,7 +473,7 @@ template <typename Acc>
 __global__ __launch_bounds__(1024) void k_reduce_test(Ctrl *c, const Acc *ps, int nbs,
                                                       const Acc *pf, int nbf) {
   if (c->done) return;
-  reduce_body<Acc>(c, ps, nbs, pf, nbf);
+  reduce_body<Acc, 1024>(c, ps, nbs, pf, nbf);
 }
 
 // Batch: one workgroup per volume. When a volume stops (converged, capped or
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(1024) void k_reduce_test_batch(const ReduceDesc *__
   const ReduceDesc d = descs[blockIdx.x];
   Ctrl *c = d.ctrl;
   if (!c->done) {
-    reduce_body<Acc>(c, (const Acc *)d.ps, d.nbs, (const Acc *)d.pf, d.nbf);
+    reduce_body<Acc, 1024>(c, (const Acc *)d.ps, d.nbs, (const Acc *)d.pf, d.nbf);
     __syncthreads();
   }
   if (threadIdx.x == 0 && c->done && !c->counted) {
