@@ -26,10 +26,23 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
   if (perm)
     for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.kofp[i];
   const float2 *in2 = reinterpret_cast<const float2 *>(d.rin);
-  for (int w = threadIdx.x; w < H * T; w += kThreads) {
-    const int i = w % H, t = w / H;
-    const long r = row0 + t;
-    lds[i * TP + t] = (r < nrows) ? in2[r * H + i] : make_float2(0.f, 0.f);
+  // all of a thread's loads are issued before its first LDS store
+  constexpr int HT = H * T, NE = (HT + kThreads - 1) / kThreads;
+  {
+    float2 v[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      const int i = w % H, t = w / H;
+      const bool ok = (HT % kThreads == 0 || w < HT) && row0 + t < nrows;
+      const float2 x = in2[(ok ? row0 + t : 0) * H + (ok ? i : 0)];
+      v[k] = ok ? x : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      if (HT % kThreads == 0 || w < HT) lds[(w % H) * TP + w / H] = v[k];
+    }
   }
   __syncthreads();
   fft_passes<H, T, TP, 0, 1>(lds, stw);
@@ -66,22 +79,37 @@ __device__ __forceinline__ void c2r_half_body(const RowDesc &d, int bid,
   if (perm)
     for (int i = threadIdx.x; i < MH; i += kThreads) sperm[i] = d.posk[i];
   __syncthreads();
-  for (int w = threadIdx.x; w < H * T; w += kThreads) {
-    const int k = w % H, t = w / H;
-    const long r = row0 + t;
-    float2 v = make_float2(0.f, 0.f);
-    if (r < nrows) {
-      const float2 xk = in[r * pitch + (perm ? sperm[k] : k)];
-      const float2 xm = in[r * pitch + (perm ? sperm[H - k] : H - k)];
-      // E = (X[k] + conj X[H-k]) / 2 ; O = e^{+2 pi i k/M} (X[k] - conj X[H-k]) / 2
-      const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
-      const float2 dd = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
-      const float2 wk = stwm[k];
-      const float2 o = cmul(make_float2(wk.x, -wk.y), dd);
-      // Z = E + i O, stored conjugated (inverse through the forward passes)
-      v = make_float2(e.x - o.y, -(e.y + o.x));
+  // all of a thread's loads are issued before the first use
+  constexpr int HT = H * T, NE = (HT + kThreads - 1) / kThreads;
+  {
+    float2 vk[NE], vm[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int w = threadIdx.x + q * kThreads;
+      const int k = w % H, t = w / H;
+      const bool ok = (HT % kThreads == 0 || w < HT) && row0 + t < nrows;
+      const long rb = (ok ? row0 + t : 0) * pitch;
+      vk[q] = in[rb + (perm ? sperm[k] : k)];
+      vm[q] = in[rb + (perm ? sperm[H - k] : H - k)];
     }
-    lds[k * TP + t] = v;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int w = threadIdx.x + q * kThreads;
+      if (!(HT % kThreads == 0 || w < HT)) continue;
+      const int k = w % H, t = w / H;
+      float2 v = make_float2(0.f, 0.f);
+      if (row0 + t < nrows) {
+        const float2 xk = vk[q], xm = vm[q];
+        // E = (X[k] + conj X[H-k]) / 2 ; O = e^{+2 pi i k/M} (X[k] - conj X[H-k]) / 2
+        const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
+        const float2 dd = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
+        const float2 wk = stwm[k];
+        const float2 o = cmul(make_float2(wk.x, -wk.y), dd);
+        // Z = E + i O, stored conjugated (inverse through the forward passes)
+        v = make_float2(e.x - o.y, -(e.y + o.x));
+      }
+      lds[k * TP + t] = v;
+    }
   }
   __syncthreads();
   fft_passes<H, T, TP, 0, 1>(lds, stw);

@@ -28,23 +28,41 @@ __device__ __forceinline__ void strided_body(const StridedDesc &d, int bid,
   float2 *data = d.data;
   const long estride = d.estride;
   stage_twiddles<N>(stw, tw);
-  for (int w = threadIdx.x; w < N * T; w += kThreads) {
-    const int i = w / T;
-    float2 v = make_float2(0.f, 0.f);
-    if (valid) {
-      v = data[base + i * estride];
-      if (INV) v.y = -v.y;
+  // Element w of the tile (line t = w % T, the thread's own) sits at lds[w].
+  // All of a thread's loads are issued before its first LDS store; a padding
+  // or out-of-range column loads from column 0 and is zeroed.
+  constexpr int NT = N * T;
+  constexpr int NE = (NT + kThreads - 1) / kThreads;
+  const long b0 = valid ? base : 0;
+  {
+    float2 v[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      const int i = (NT % kThreads == 0 || w < NT) ? w / T : 0;
+      const float2 x = data[b0 + i * estride];
+      v[k] = valid ? make_float2(x.x, INV ? -x.y : x.y) : make_float2(0.f, 0.f);
     }
-    lds[i * T + t] = v;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      if (NT % kThreads == 0 || w < NT) lds[w] = v[k];
+    }
   }
   __syncthreads();
   fft_passes<N, T, T, 0, 1>(lds, stw);
   if (valid) {
-    for (int w = threadIdx.x; w < N * T; w += kThreads) {
-      const int i = w / T;
-      float2 v = lds[i * T + t];
-      if (INV) v.y = -v.y;
-      data[base + i * estride] = v;
+    float2 v[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      if (NT % kThreads == 0 || w < NT) v[k] = lds[w];
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int w = threadIdx.x + k * kThreads;
+      if (NT % kThreads == 0 || w < NT)
+        data[base + (w / T) * estride] = make_float2(v[k].x, INV ? -v[k].y : v[k].y);
     }
   }
 }
