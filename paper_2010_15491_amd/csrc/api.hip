@@ -1097,8 +1097,10 @@ int sr3d_autotune(const sr3d_problem *p, int count, int force, hipStream_t st) {
   }
   for (int i = 0; i < count; ++i) {
     check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &g);
-    SR3D_TRY(fft_autotune(g.S, g.N, g.M, force != 0, st), "autotune HR");
-    SR3D_TRY(fft_autotune(g.Sl, g.Nl, g.Ml, force != 0, st), "autotune LR");
+    // the m and n passes are timed in the layout the solver runs them in
+    SR3D_TRY(fft_autotune(g.S, g.N, g.M, g.sp.fused ? g.sp.pitch : 0, force != 0, st),
+             "autotune HR");
+    SR3D_TRY(fft_autotune(g.Sl, g.Nl, g.Ml, 0, force != 0, st), "autotune LR");
   }
   return SR3D_OK;
 }

@@ -147,14 +147,18 @@ static bool fft_tuned(int kind, int len) {
 }
 
 // One launch of axis kernel `kind` over a volume S x N x M with variant v.
+// pitch: spectrum row pitch of the m and n kinds (0: M/2 + 1, the natural
+// layout); the s kinds always use the natural layout.
 static hipError_t launch_kind(int kind, int v, const float *rin, float *rout, float2 *spec, int S,
-                              int N, int M, float scale, const int *done, hipStream_t st) {
+                              int N, int M, float scale, const int *done, hipStream_t st,
+                              int pitch = 0) {
   const long Mh = M / 2 + 1;
+  const long P = pitch > 0 ? pitch : Mh;
   switch (kind) {
-    case kFftR2cM: return launch_r2c_m_v(rin, spec, (long)S * N, M, v, done, st);
-    case kFftC2rM: return launch_c2r_m_v(spec, rout, (long)S * N, M, scale, v, done, st);
-    case kFftFwdN: return launch_strided_v(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, false, v, done, st);
-    case kFftInvN: return launch_strided_v(spec, N, (long)S * Mh, Mh, (long)N * Mh, Mh, true, v, done, st);
+    case kFftR2cM: return launch_r2c_m_v(rin, spec, (long)S * N, M, v, done, st, nullptr, nullptr, (int)(pitch > 0 ? pitch : 0));
+    case kFftC2rM: return launch_c2r_m_v(spec, rout, (long)S * N, M, scale, v, done, st, nullptr, nullptr, (int)(pitch > 0 ? pitch : 0));
+    case kFftFwdN: return launch_strided_v(spec, N, (long)S * P, P, (long)N * P, P, false, v, done, st, Mh);
+    case kFftInvN: return launch_strided_v(spec, N, (long)S * P, P, (long)N * P, P, true, v, done, st, Mh);
     case kFftFwdS: return launch_strided_v(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, false, v, done, st);
     case kFftInvS: return launch_strided_v(spec, S, (long)N * Mh, (long)N * Mh, 0, (long)N * Mh, true, v, done, st);
     default: return hipErrorInvalidValue;
@@ -165,10 +169,11 @@ static int kind_len(int kind, int S, int N, int M) {
   return (kind <= kFftC2rM) ? M : (kind <= kFftInvN) ? N : S;
 }
 
-hipError_t fft_autotune(int S, int N, int M, bool force, hipStream_t st) {
+hipError_t fft_autotune(int S, int N, int M, int pitch, bool force, hipStream_t st) {
   hipError_t e = ensure_device_tables();
   if (e != hipSuccess) return e;
-  const long NT = (long)S * N * M, nspec = (long)S * N * (M / 2 + 1);
+  const long Mh = M / 2 + 1;
+  const long NT = (long)S * N * M, nspec = (long)S * N * (pitch > Mh ? pitch : Mh);
   float *real = nullptr;
   float2 *spec = nullptr;
   if ((e = hipMalloc(&real, sizeof(float) * NT)) != hipSuccess) return e;
@@ -187,10 +192,11 @@ hipError_t fft_autotune(int S, int N, int M, bool force, hipStream_t st) {
     float best = 1e30f;
     int bv = 1;
     for (int v = 0; e == hipSuccess && v < kTileVariants; ++v) {
-      e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st);
+      const int kp = (kind == kFftFwdS || kind == kFftInvS) ? 0 : pitch;
+      e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st, kp);
       if (e == hipSuccess) e = hipEventRecord(e0, st);
       for (int r = 0; e == hipSuccess && r < 5; ++r)
-        e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st);
+        e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st, kp);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

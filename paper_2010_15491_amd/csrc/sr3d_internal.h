@@ -119,7 +119,8 @@ void fft_set_variant(int kind, int len, int v);
 // Times every tile variant of every axis kernel a volume S x N x M uses and
 // keeps the fastest (skips lengths already tuned unless force). Allocates
 // scratch with hipMalloc and synchronises the stream.
-hipError_t fft_autotune(int S, int N, int M, bool force, hipStream_t st);
+// pitch: row pitch the m and n kinds are timed with (0: natural layout).
+hipError_t fft_autotune(int S, int N, int M, int pitch, bool force, hipStream_t st);
 int fft_tune_save(const char *path);
 int fft_tune_load(const char *path);
 // Device twiddle table exp(-2 pi i k / n), k < n, for the current device.
