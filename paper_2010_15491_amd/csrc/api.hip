@@ -354,14 +354,22 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   return admm_stencil(sa, false, false, st);
 }
 
-// Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2].
+// Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2]. The
+// stopping test of an iteration runs in an extra workgroup of the next
+// iteration's first launch (fused path, not the first iteration of an
+// enqueued chunk: `merged`), or in its own launch at the end of a chunk
+// (`last`), so the host sees complete statistics after every chunk.
 hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
-                        int k, bool fp64, hipStream_t st) {
+                        int k, bool fp64, hipStream_t st, bool merged, bool last) {
   const int *done = &L.ctrl->done;
   hipError_t e;
+  // the R2C launch can carry the reduction (m = 1 uses a plain copy kernel)
+  const bool carry = L.fused && g.M > 1;
   if (L.fused) {
     const int *kofp = L.tab, *posk = L.tab + g.Mh;
-    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st)))
+    const RedArgs red{L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64 ? 1 : 0};
+    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st,
+                              carry && merged ? &red : nullptr)))
       return e;
     prof_begin(kStSolveS, st);
     e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
@@ -384,6 +392,7 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
   sa.part = L.partS; sa.done = done;
   if ((e = admm_stencil(sa, true, fp64, st))) return e;
+  if (carry && !last) return hipSuccess;  // reduced by the next iteration's R2C launch
   return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
 }
 
@@ -423,7 +432,8 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int i = 1; e == hipSuccess && i <= K; ++i) e = tv_iteration(g, L, p, nu, i, fp64, cs);
+    for (int i = 1; e == hipSuccess && i <= K; ++i)
+      e = tv_iteration(g, L, p, nu, i, fp64, cs, i > 1, i == K);
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -446,7 +456,8 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   } else {
     for (int it = 0; it < p->max_iter;) {
       const int n = (p->max_iter - it) < K ? (p->max_iter - it) : K;
-      for (int i = 1; i <= n; ++i) SR3D_TRY(tv_iteration(g, L, p, nu, it + i, fp64, st), "tv iteration");
+      for (int i = 1; i <= n; ++i)
+        SR3D_TRY(tv_iteration(g, L, p, nu, it + i, fp64, st, i > 1, i == n), "tv iteration");
       it += n;
       SR3D_TRY(hipMemcpyAsync(hc, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "ctrl copy");
       SR3D_TRY(hipStreamSynchronize(st), "stream sync");

@@ -290,10 +290,11 @@ static hipError_t run_n_pitched(bool inv, float2 *spec, int S, int N, int M, int
 }
 
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
-                            const int *posk, int pitch, const int *done, hipStream_t st) {
+                            const int *posk, int pitch, const int *done, hipStream_t st,
+                            const RedArgs *red) {
   prof_begin(kStFftR2cM, st);
   hipError_t e = launch_r2c_m_v(in, spec, (long)S * N, M, fft_variant(kFftR2cM, M), done, st,
-                                kofp, posk, pitch);
+                                kofp, posk, pitch, red);
   prof_end(st);
   if (e == hipSuccess) e = run_n_pitched(false, spec, S, N, M, pitch, done, st);
   return e;

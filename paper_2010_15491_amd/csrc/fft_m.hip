@@ -8,6 +8,7 @@
 // the real row as a complex one. A workgroup transforms T rows (T from the
 // tile size the autotuner picked); rows are read and written coalesced.
 #include "fft_core.h"
+#include "reduce.h"
 
 namespace sr3d {
 
@@ -205,8 +206,15 @@ __device__ __forceinline__ void row_body(const RowDesc &d, int bid, const float2
 template <int M, int E, bool C2R>
 __global__ __launch_bounds__(kThreads) void k_fft_rows(RowDesc d, const float2 *__restrict__ twh,
                                                        const float2 *__restrict__ twm) {
+  // With a reduction attached, workgroup 0 (dispatched first, so it overlaps
+  // the transform) runs the previous iteration's stopping test.
+  const bool red = !C2R && d.red.ctrl;
+  if (red && blockIdx.x == 0) {
+    reduce_in_block(d.red);
+    return;
+  }
   if (d.done && *d.done) return;
-  row_body<M, E, C2R>(d, blockIdx.x, twh, twm);
+  row_body<M, E, C2R>(d, (int)blockIdx.x - (red ? 1 : 0), twh, twm);
 }
 
 template <int M, int E, bool C2R>
@@ -244,7 +252,7 @@ template <int M, int E>
 static void launch_rows_t(const RowDesc &d, bool c2r, hipStream_t st) {
   constexpr int T = row_tile_lines(M, E);
   const float2 *twh = (M % 2 == 0) ? twiddles(M / 2) : nullptr;
-  dim3 g((unsigned)((d.nrows + T - 1) / T));
+  dim3 g((unsigned)((d.nrows + T - 1) / T + (d.red.ctrl && !c2r ? 1 : 0)));
   if (c2r) hipLaunchKernelGGL((k_fft_rows<M, E, true>), g, dim3(kThreads), 0, st, d, twh, twiddles(M));
   else hipLaunchKernelGGL((k_fft_rows<M, E, false>), g, dim3(kThreads), 0, st, d, twh, twiddles(M));
 }
@@ -307,15 +315,16 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
 }
 
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
-                          hipStream_t st, const int *kofp, const int *posk, int pitch) {
+                          hipStream_t st, const int *kofp, const int *posk, int pitch,
+                          const RedArgs *red) {
   if (M == 1) {
-    if (pitch > 1) return hipErrorInvalidValue;
+    if (pitch > 1 || red) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy_r2c1, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, in,
                        out, nrows, done);
     return hipGetLastError();
   }
   if (M % 2) kofp = posk = nullptr;  // odd M: every class order is the natural one
-  RowDesc d{in, out, nullptr, nrows, 1.0f, done, kofp, posk, pitch};
+  RowDesc d{in, out, nullptr, nrows, 1.0f, done, kofp, posk, pitch, red ? *red : RedArgs{}};
   return launch_rows(d, M, false, v, st);
 }
 

@@ -86,6 +86,16 @@ inline StridedDesc make_strided_desc(float2 *data, long ncols, long inner, long 
   d.done = done;
   return d;
 }
+// Final reduction and stopping test of an iteration, run by one extra
+// workgroup of another launch (ctrl == nullptr: none).
+struct RedArgs {
+  Ctrl *ctrl;
+  const void *ps;  // stencil partials [6][nbs]
+  int nbs;
+  const void *pf;  // data-term partials [nbf]
+  int nbf;
+  int fp64;        // partials are double (else float)
+};
 struct RowDesc {
   const float *rin;  // R2C input rows
   float2 *spec;      // half-spectrum rows (R2C output / C2R input)
@@ -97,6 +107,7 @@ struct RowDesc {
   // frequency k_m held at position p, posk its inverse. Null: natural order.
   const int *kofp, *posk;
   int pitch;  // complex entries between spectrum rows (0: M/2 + 1)
+  RedArgs red;  // R2C: the previous iteration's final reduction, in one extra workgroup
 };
 int strided_tiles(int L, int v, long ncols);
 int row_tiles(int M, int v, long nrows);
@@ -107,7 +118,7 @@ hipError_t launch_rows_batch(int M, bool c2r, int v, const RowDesc *descs, const
 enum FftKind { kFftR2cM, kFftC2rM, kFftFwdN, kFftInvN, kFftFwdS, kFftInvS, kFftKinds };
 hipError_t launch_r2c_m_v(const float *in, float2 *out, long nrows, int M, int v, const int *done,
                           hipStream_t st, const int *kofp = nullptr, const int *posk = nullptr,
-                          int pitch = 0);
+                          int pitch = 0, const RedArgs *red = nullptr);
 hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float scale, int v,
                           const int *done, hipStream_t st, const int *kofp = nullptr,
                           const int *posk = nullptr, int pitch = 0);
@@ -137,7 +148,8 @@ hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float sc
 // The m and n passes alone (the s axis is left to the fused x-update), with
 // the m columns stored in the order kofp / posk and rows `pitch` apart.
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
-                            const int *posk, int pitch, const int *done, hipStream_t st);
+                            const int *posk, int pitch, const int *done, hipStream_t st,
+                            const RedArgs *red = nullptr);
 hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                             const int *kofp, const int *posk, int pitch, const int *done,
                             hipStream_t st);
