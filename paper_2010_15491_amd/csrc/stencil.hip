@@ -331,7 +331,9 @@ StencilPlan stencil_plan(int S, int N, int M) {
   p.tiles_m = (M + FT_M - 1) / FT_M;
   p.tiles_n = (N + FT_N - 1) / FT_N;
   const long cols = (long)p.tiles_m * p.tiles_n;
-  long L = (S * cols + 2047) / 2048;
+  // planes per workgroup: about 1024 workgroups, 2..32 planes (the s-halo
+  // re-read is 2 planes per chunk)
+  long L = (S * cols + 1023) / 1024;
   if (L < 2) L = 2;
   if (L > 32) L = 32;
   if (L > S) L = S;
