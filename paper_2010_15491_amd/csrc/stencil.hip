@@ -8,7 +8,7 @@
 // writes nu_new and Theta (32 bytes per voxel); nu is double-buffered because
 // neighbouring workgroups read nu_old across tile borders.
 //
-// A workgroup owns a 16 (n) x 32 (m) column tile and marches along s through
+// A workgroup owns an 8 (n) x 64 (m) column tile and marches along s through
 // a chunk of planes. Per plane it stages x with a one-voxel ring in LDS
 // (forward differences), recomputes nu_new, u, d on the tile plus its lower
 // n and m faces (the backward neighbours L^T needs), and keeps the s-component
@@ -59,7 +59,7 @@ __device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr,
   u2 = a2 * s;
 }
 
-constexpr int FT_M = 32, FT_N = 16, FT_COLS = FT_M * FT_N;  // tile columns (2 per thread)
+constexpr int FT_M = 64, FT_N = 8, FT_COLS = FT_M * FT_N;  // tile columns (2 per thread)
 constexpr int XR_M = FT_M + 2, XR_N = FT_N + 2, XR = XR_M * XR_N;  // x plane with ring
 constexpr int FF_M = FT_M + 1, FF_N = FT_N + 1, FF = FF_M * FF_N;  // tile + lower faces
 constexpr int NFACE = FF - FT_COLS;
