@@ -260,13 +260,12 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     }
     // Store X_q (already scaled by 1/N_h), conjugated for the inverse pass,
     // at the stored member, and conj at the partner's stored -k.
+    // Branch-free: a store with no target goes to the spare entry lds[S*T].
     auto emit = [&](int q, float2 xs) {
-      if (li[q] >= 0) {
-        lds[li[q]] = make_float2(xs.x, -xs.y);
-        if (mi[q] >= 0) lds[mi[q]] = xs;
-      } else if (!g.selfc) {
-        lds[-1 - li[q]] = xs;
-      }
+      const bool direct = li[q] >= 0;
+      const int a1 = direct ? li[q] : (g.selfc ? S * T : -1 - li[q]);
+      lds[a1] = direct ? make_float2(xs.x, -xs.y) : xs;
+      lds[mi[q] >= 0 ? mi[q] : S * T] = xs;
     };
     float2 mean;  // (1/d) sum_b L_b X_b of the new x, for the data residual
     if (g.js == 0 && g.jn == 0 && g.jm == 0) {
@@ -396,7 +395,7 @@ __global__ __launch_bounds__(kThreads, (DM <= 8 ? 2 : 1)) void k_solve_s(const S
   const SolveSArgs a = descs[v];
   if (a.done && *a.done) return;
   constexpr int T = solve_tile(S);
-  __shared__ float2 lds[S * T];
+  __shared__ float2 lds[S * T + 1];  // + a spare entry for stores without a target
   __shared__ float2 stw[S];
   __shared__ float sgs[S];
   __shared__ UnitTabs ut;
