@@ -77,9 +77,9 @@ __device__ __forceinline__ int block_classes(const int *mj, int CB) {
   while (nc < CB && mj[nc] >= 0) ++nc;
   return nc;
 }
-__device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, int nc, int j0,
-                                           int j1, int slot, SlotGroup &g) {
-  const int ci = slot % nc, r1 = slot / nc;
+// Slot = r1 * nc + ci with r1 = 2 js + ji.
+__device__ __forceinline__ bool slot_group_at(const SolveSArgs &a, const int *mj, int ci, int r1,
+                                              int j0, int j1, SlotGroup &g) {
   const int ji = r1 & 1, js = r1 >> 1;
   const int jm = mj[ci];
   if (jm < 0 || (ji && j1 < 0)) return false;
@@ -93,6 +93,10 @@ __device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, i
   }
   g = SlotGroup{js, jn, jm, ji, ci, selfc};
   return true;
+}
+__device__ __forceinline__ bool slot_group(const SolveSArgs &a, const int *mj, int nc, int j0,
+                                           int j1, int slot, SlotGroup &g) {
+  return slot_group_at(a, mj, slot % nc, slot / nc, j0, j1, g);
 }
 
 // LDS side tables of a unit (sizes bound the plan: lines <= 64, classes per
@@ -207,7 +211,11 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     for (int q = 0; q < DM; ++q)
       if (q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + threadIdx.x]);
   }
+  // slot -> (ci, r1) advanced incrementally: kThreads = dq * nc + dr
+  const int dq = kThreads / nc, dr = kThreads - dq * nc;
+  int sci = (int)threadIdx.x % nc, sr1 = (int)threadIdx.x / nc;
   for (int slot = threadIdx.x; slot < gcount; slot += kThreads) {
+    const int ci = sci;
     float2 lcur[DM];
 #pragma unroll
     for (int q = 0; q < DM; ++q) lcur[q] = lnext[q];
@@ -220,7 +228,14 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
         if (q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
     }
     SlotGroup g;
-    if (!slot_group(a, ut.mj, nc, j0, j1, slot, g)) continue;
+    const bool ok = slot_group_at(a, ut.mj, ci, sr1, j0, j1, g);
+    sci += dr;
+    sr1 += dq;
+    if (sci >= nc) {
+      sci -= nc;
+      ++sr1;
+    }
+    if (!ok) continue;
     // Members: Lambda, B = conj(Lambda) Y + mu W, A = mu G, the LDS index of
     // the stored entry (li >= 0: the member itself, else -1-index of its
     // mirror) and, for a stored member whose -k is stored as well and belongs
