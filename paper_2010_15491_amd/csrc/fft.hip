@@ -174,29 +174,46 @@ hipError_t fft_autotune(int S, int N, int M, int pitch, bool force, hipStream_t 
   if (e != hipSuccess) return e;
   const long Mh = M / 2 + 1;
   const long NT = (long)S * N * M, nspec = (long)S * N * (pitch > Mh ? pitch : Mh);
-  float *real = nullptr;
-  float2 *spec = nullptr;
-  if ((e = hipMalloc(&real, sizeof(float) * NT)) != hipSuccess) return e;
-  if ((e = hipMalloc(&spec, sizeof(float2) * nspec)) != hipSuccess) {
-    (void)hipFree(real);
-    return e;
-  }
+  // Successive timed launches work on different buffers, together larger
+  // than the GPU's last-level cache, so the timings include the HBM traffic
+  // each tile shape really causes.
+  const size_t rbytes = ((sizeof(float) * NT + 255) / 256) * 256;
+  const size_t sbytes = ((sizeof(float2) * nspec + 255) / 256) * 256;
+  const size_t per = rbytes + sbytes;
+  int nbuf = (int)(((size_t)640 << 20) / per) + 1;
+  if (nbuf > 8) nbuf = 8;
+  char *pool = nullptr;
+  if ((e = hipMalloc(&pool, per * nbuf)) != hipSuccess) return e;
+  auto real_of = [&](int r) { return reinterpret_cast<float *>(pool + per * (r % nbuf)); };
+  auto spec_of = [&](int r) { return reinterpret_cast<float2 *>(pool + per * (r % nbuf) + rbytes); };
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  e = hipMemsetAsync(real, 0, sizeof(float) * NT, st);
-  if (e == hipSuccess) e = hipMemsetAsync(spec, 0, sizeof(float2) * nspec, st);
+  e = hipMemsetAsync(pool, 0, per * nbuf, st);
+  int r = 0;
   for (int kind = 0; e == hipSuccess && kind < kFftKinds; ++kind) {
     const int len = kind_len(kind, S, N, M);
     if (len <= 1 || (!force && fft_tuned(kind, len))) continue;
     float best = 1e30f;
     int bv = 1;
+    // Strided passes move T-column row segments: only tiles whose segments
+    // fill whole 128-byte lines (T >= 16) are candidates when one exists.
+    // Narrower segments fetch each line twice, which an isolated timing of
+    // a cache-resident buffer does not show.
+    const bool strided = kind >= kFftFwdN;
+    int tmax = 1;
+    for (int v = 0; v < kTileVariants; ++v)
+      tmax = tile_lines(len, kTileElems[v]) > tmax ? tile_lines(len, kTileElems[v]) : tmax;
+    const int tmin = strided ? (tmax < 16 ? tmax : 16) : 1;
     for (int v = 0; e == hipSuccess && v < kTileVariants; ++v) {
+      if (tile_lines(len, kTileElems[v]) < tmin) continue;
       const int kp = (kind == kFftFwdS || kind == kFftInvS) ? 0 : pitch;
-      e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st, kp);
+      e = launch_kind(kind, v, real_of(r), real_of(r), spec_of(r), S, N, M, 1.0f, nullptr, st, kp);
+      ++r;
       if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int r = 0; e == hipSuccess && r < 5; ++r)
-        e = launch_kind(kind, v, real, real, spec, S, N, M, 1.0f, nullptr, st, kp);
+      for (int k = 0; e == hipSuccess && k < 5; ++k, ++r)
+        e = launch_kind(kind, v, real_of(r), real_of(r), spec_of(r), S, N, M, 1.0f, nullptr, st,
+                        kp);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -211,8 +228,7 @@ hipError_t fft_autotune(int S, int N, int M, int pitch, bool force, hipStream_t 
   (void)hipStreamSynchronize(st);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(real);
-  (void)hipFree(spec);
+  (void)hipFree(pool);
   return e;
 }
 

@@ -129,7 +129,9 @@ int fft_variant(int kind, int len);
 void fft_set_variant(int kind, int len, int v);
 // Times every tile variant of every axis kernel a volume S x N x M uses and
 // keeps the fastest (skips lengths already tuned unless force). Allocates
-// scratch with hipMalloc and synchronises the stream.
+// scratch with hipMalloc (up to 8 volume-sized buffers, at least 640 MiB
+// together, rotated so timings include HBM traffic) and synchronises the
+// stream.
 // pitch: row pitch the m and n kinds are timed with (0: natural layout).
 hipError_t fft_autotune(int S, int N, int M, int pitch, bool force, hipStream_t st);
 int fft_tune_save(const char *path);
