@@ -360,6 +360,10 @@ FUSE_CASES = [
     ((32, 16, 1), (1, 2, 2)),
     ((8, 16, 16), (2, 2, 2)),
     ((64, 32, 32), (2, 2, 4)),
+    ((512, 8, 8), (2, 2, 2)),
+    ((384, 8, 8), (2, 2, 4)),
+    ((192, 24, 24), (2, 2, 2)),
+    ((128, 32, 32), (4, 4, 2)),
 ]
 
 
