@@ -60,6 +60,8 @@ def alg_bytes_per_voxel(stage, hr, rate):
         "solve_s": 3 * spec + 8.0 * mlh / d,
         # x and nu_old (3 planes) read; nu_new (3 planes) and Theta written
         "admm_stencil": 4.0 + 12.0 + 12.0 + 4.0,
+        # the same with the m-axis R2C fused in: Theta's half spectrum written
+        "stencil_r2c": 4.0 + 12.0 + 12.0 + spec,
     }
     return table.get(stage)
 

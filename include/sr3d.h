@@ -89,7 +89,7 @@ typedef struct {
 /* flags for sr3d_tv_admm / sr3d_batch */
 #define SR3D_FP64_REDUCE 0x1   /* residual/objective reductions and the stopping test in FP64 (else FP32);
                                   per-voxel terms are FP32 and each thread first sums its
-                                  own (at most 64 per stencil thread) in FP32 */
+                                  own (at most 256 per stencil thread) in FP32 */
 #define SR3D_RESUME      0x2   /* start from problem.state (must be non-NULL) */
 #define SR3D_USE_GRAPH   0x4   /* replay captured iterations as a HIP graph */
 #define SR3D_PROFILE     0x8   /* time every kernel launch with HIP events on the caller's
@@ -100,6 +100,10 @@ typedef struct {
 #define SR3D_UNFUSED     0x20  /* run the x-update as separate s-FFT, fold/solve and inverse
                                   s-FFT kernels even where the fused s-line kernel applies
                                   (same result up to FP32 rounding; for testing) */
+#define SR3D_SEPARATE_R2C 0x40 /* with the fused x-update: run the stencil and the m-axis
+                                  R2C of the next x-update as separate kernels even where the
+                                  row length admits the fused stencil (64, 128, 192, 256,
+                                  384, 512); same bits, for testing */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */

@@ -32,7 +32,7 @@ long g_prof_n[kStCount] = {0};
 unsigned g_prof_mask = ~0u;  // stages timed under SR3D_PROFILE
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
                                      "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
-                                     "reduce_test", "solve_s", "setup"};
+                                     "reduce_test", "solve_s", "stencil_r2c", "setup"};
 }  // namespace
 
 void prof_begin(int stage, hipStream_t st) {
@@ -184,7 +184,9 @@ struct TvWs {
   int *tab;
   SolveSArgs *sdesc;
   int nbS, nbF, nbFold, nbFused;
+  int nbStile, nbSrow;  // stencil workgroups: tiled kernel, fused stencil + R2C kernel
   bool fused;  // this solve uses the fused x-update (set by the caller)
+  bool fsten;  // ... and the stencil with the m-axis R2C fused in
 };
 
 // Workspace of one TV solve. nu[0] is only used when the caller passes no
@@ -192,7 +194,10 @@ struct TvWs {
 // fused plan, so the size does not depend on the flags.
 size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   Carve c{base, 0};
-  L->nbS = stencil_plan(g.S, g.N, g.M).blocks;
+  L->nbStile = stencil_plan(g.S, g.N, g.M).blocks;
+  L->nbSrow = g.sp.fused && stencil_r2c_supported(g.M) ? stencil_r2c_plan(g.S, g.N, g.M).blocks : 0;
+  L->nbS = L->nbStile;
+  L->fsten = false;
   FoldArgs fa{};
   fa.Sl = g.Sl; fa.Nl = g.Nl; fa.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
   L->nbFold = fold_blocks(fa);
@@ -200,7 +205,7 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->nbF = L->nbFold;
   L->fused = false;
   L->ctrl = c.take<Ctrl>(1);
-  L->partS = c.take<double>((size_t)6 * L->nbS);
+  L->partS = c.take<double>((size_t)6 * (L->nbStile > L->nbSrow ? L->nbStile : L->nbSrow));
   L->partF = c.take<double>((size_t)(L->nbFold > L->nbFused ? L->nbFold : L->nbFused));
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
   L->lam = c.take<float2>(g.nspec);
@@ -223,9 +228,13 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   return c.off + 256;
 }
 
+// The batch launches the tiled stencil for every volume (one launch for the
+// batch), so it passes SR3D_SEPARATE_R2C.
 void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->fused = g.sp.fused && !(flags & SR3D_UNFUSED);
   L->nbF = L->fused ? L->nbFused : L->nbFold;
+  L->fsten = L->fused && L->nbSrow > 0 && !(flags & SR3D_SEPARATE_R2C);
+  L->nbS = L->fsten ? L->nbSrow : L->nbStile;
 }
 
 SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem *p) {
@@ -311,6 +320,18 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
   return SR3D_OK;
 }
 
+// With the fused stencil, every iteration starts from the m-transformed Theta
+// in w (the previous stencil writes it), so the setup leaves Theta0 there too.
+hipError_t theta0_spectrum(const Geometry &g, const TvWs &L, hipStream_t st) {
+  if (!L.fsten) return hipSuccess;
+  prof_begin(kStFftR2cM, st);
+  const hipError_t e = launch_r2c_m_v(L.theta, L.w, (long)g.S * g.N, g.M,
+                                      fft_variant(kFftR2cM, g.M), nullptr, st, L.tab,
+                                      L.tab + g.Mh, g.sp.pitch, nullptr);
+  prof_end(st);
+  return e;
+}
+
 // Enqueue setup and initial state (nu in nu0, Theta) for one TV problem.
 hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *nu0, int flags,
                     hipStream_t st) {
@@ -333,7 +354,10 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
     if ((e = hipStreamSynchronize(st))) return e;  // the host images above are locals
   }
   const float thr = p->lambda_tv / p->mu;
-  if (flags & SR3D_RESUME) return theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st);
+  if (flags & SR3D_RESUME) {
+    if ((e = theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st))) return e;
+    return theta0_spectrum(g, L, st);
+  }
   const float *xinit = p->x0;
   if (p->x0 && (flags & SR3D_WARM_DUAL)) {
     // nu0 = L (x0 + phi): u0 = shrink(nu0), d0 = nu0 - u0 start from the
@@ -351,7 +375,8 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   AdmmStencilArgs sa{};
   sa.x = xinit; sa.nu_in = nullptr; sa.nu_out = nu0; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = thr; sa.part = nullptr; sa.done = nullptr;
-  return admm_stencil(sa, false, false, st);
+  if ((e = admm_stencil(sa, false, false, st))) return e;
+  return theta0_spectrum(g, L, st);
 }
 
 // Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2]. The
@@ -363,14 +388,19 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
                         int k, bool fp64, hipStream_t st, bool merged, bool last) {
   const int *done = &L.ctrl->done;
   hipError_t e;
-  // the R2C launch can carry the reduction (m = 1 uses a plain copy kernel)
-  const bool carry = L.fused && g.M > 1;
+  // The iteration's first launch can carry the previous reduction: the R2C
+  // (m = 1 uses a plain copy kernel), or with the fused stencil, whose m pass
+  // is already done, the n pass (none for n = 1).
+  const bool carry = L.fsten ? g.N > 1 : L.fused && g.M > 1;
   if (L.fused) {
     const int *kofp = L.tab, *posk = L.tab + g.Mh;
     const RedArgs red{L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64 ? 1 : 0};
-    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st,
-                              carry && merged ? &red : nullptr)))
-      return e;
+    if (L.fsten)
+      e = fft_n_forward(L.w, g.S, g.N, g.M, g.sp.pitch, done, st, carry && merged ? &red : nullptr);
+    else
+      e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st,
+                           carry && merged ? &red : nullptr);
+    if (e) return e;
     prof_begin(kStSolveS, st);
     e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
@@ -391,8 +421,12 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
   sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
   sa.part = L.partS; sa.done = done;
-  if ((e = admm_stencil(sa, true, fp64, st))) return e;
-  if (carry && !last) return hipSuccess;  // reduced by the next iteration's R2C launch
+  if (L.fsten)
+    e = admm_stencil_r2c(sa, L.w, L.tab, g.sp.pitch, fp64, st);
+  else
+    e = admm_stencil(sa, true, fp64, st);
+  if (e) return e;
+  if (carry && !last) return hipSuccess;  // reduced by the next iteration's first launch
   return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
 }
 
@@ -714,7 +748,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   std::vector<TvWs> Ls(count);
   for (int i = 0; i < count; ++i) {
     tv_layout(g[i], base + offs[i], &Ls[i]);
-    tv_choose_path(g[i], flags, &Ls[i]);
+    tv_choose_path(g[i], flags | SR3D_SEPARATE_R2C, &Ls[i]);
   }
   Ctrl *hc = host_ctrl();
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");

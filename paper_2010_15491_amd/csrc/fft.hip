@@ -295,14 +295,19 @@ hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float sc
 
 // n-axis pass over a spectrum with rows `pitch` apart (padding columns skipped).
 static hipError_t run_n_pitched(bool inv, float2 *spec, int S, int N, int M, int pitch,
-                                const int *done, hipStream_t st) {
-  if (N == 1) return hipSuccess;
+                                const int *done, hipStream_t st, const RedArgs *red = nullptr) {
+  if (N == 1) return red ? hipErrorInvalidValue : hipSuccess;
   const int kind = inv ? kFftInvN : kFftFwdN;
   prof_begin(inv ? kStIfftN : kStFftN, st);
   const hipError_t e = launch_strided_v(spec, N, (long)S * pitch, pitch, (long)N * pitch, pitch,
-                                        inv, fft_variant(kind, N), done, st, M / 2 + 1);
+                                        inv, fft_variant(kind, N), done, st, M / 2 + 1, red);
   prof_end(st);
   return e;
+}
+
+hipError_t fft_n_forward(float2 *spec, int S, int N, int M, int pitch, const int *done,
+                         hipStream_t st, const RedArgs *red) {
+  return run_n_pitched(false, spec, S, N, M, pitch, done, st, red);
 }
 
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,

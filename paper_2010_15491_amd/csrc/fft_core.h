@@ -36,7 +36,12 @@ constexpr int tile_lines(int N, int E) {
 constexpr int kTileVariants = 3;
 constexpr int kTileElems[kTileVariants] = {2048, 4096, 8192};
 
+// The FFT arithmetic below is never contracted into FMAs: whether the
+// compiler would fuse a product into a later sum depends on the surrounding
+// code (unrolling, tile shape), and every kernel that runs these transforms
+// must produce the same bits for the same line.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+#pragma clang fp contract(off)
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -54,6 +59,7 @@ template <> __device__ __forceinline__ void butterfly<2>(float2 *v) {
 }
 
 template <> __device__ __forceinline__ void butterfly<3>(float2 *v) {
+#pragma clang fp contract(off)
   const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
   float2 s = cadd(v[1], v[2]);
   float2 d = csub(v[1], v[2]);
@@ -76,6 +82,7 @@ template <> __device__ __forceinline__ void butterfly<4>(float2 *v) {
 }
 
 template <> __device__ __forceinline__ void butterfly<8>(float2 *v) {
+#pragma clang fp contract(off)
   const float c = 0.70710678118654752440f;
   float2 e[4] = {v[0], v[2], v[4], v[6]};
   float2 o[4] = {v[1], v[3], v[5], v[7]};
@@ -141,6 +148,19 @@ __device__ __forceinline__ void fft_passes(float2 *lds, const float2 *tw) {
     fft_pass<N, T, TP, R, NS>(lds, tw);
     fft_passes<N, T, TP, P + 1, NS * R>(lds, tw);
   }
+}
+
+// Half-length real transform, last step: the length-M spectrum entry k from
+// the length-M/2 complex spectrum Z of z[i] = x[2i] + i x[2i+1]:
+//   X[k] = (Z[k] + conj Z[M/2-k]) / 2 - i e^{-2 pi i k/M} (Z[k] - conj Z[M/2-k]) / 2,
+// with zk = Z[k mod M/2], zm = Z[(M/2-k) mod M/2] and wk = e^{-2 pi i k/M}.
+// Every R2C kernel ends with this function.
+__device__ __forceinline__ float2 r2c_post(float2 zk, float2 zm, float2 wk) {
+#pragma clang fp contract(off)
+  const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+  const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+  const float2 wo = cmul(wk, o);
+  return make_float2(e.x + wo.x, e.y + wo.y);
 }
 
 template <int N>

@@ -53,13 +53,7 @@ __device__ __forceinline__ void r2c_half_body(const RowDesc &d, int bid,
     const long r = row0 + t;
     if (r < nrows) {
       const int k = perm ? sperm[p] : p;
-      const float2 zk = lds[(k % H) * TP + t];
-      const float2 zm = lds[((H - k) % H) * TP + t];
-      // E = (Z[k] + conj Z[H-k]) / 2 ; O = -i (Z[k] - conj Z[H-k]) / 2
-      const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-      const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      const float2 wo = cmul(stwm[k], o);
-      out[r * pitch + p] = make_float2(e.x + wo.x, e.y + wo.y);
+      out[r * pitch + p] = r2c_post(lds[(k % H) * TP + t], lds[((H - k) % H) * TP + t], stwm[k]);
     }
   }
 }

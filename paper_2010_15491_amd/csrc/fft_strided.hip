@@ -7,6 +7,7 @@
 // moves is T consecutive complex values; the lines are transformed in LDS
 // (t fastest across lanes) and written back to the same places.
 #include "fft_core.h"
+#include "reduce.h"
 
 namespace sr3d {
 
@@ -70,11 +71,18 @@ __device__ __forceinline__ void strided_body(const StridedDesc &d, int bid,
 template <int N, bool INV, int E>
 __global__ __launch_bounds__(kThreads) void k_fft_strided(StridedDesc d,
                                                           const float2 *__restrict__ tw) {
+  // With a reduction attached, workgroup 0 (dispatched first, so it overlaps
+  // the transform) runs the previous iteration's stopping test.
+  const bool red = d.red.ctrl != nullptr;
+  if (red && blockIdx.x == 0) {
+    reduce_in_block(d.red);
+    return;
+  }
   if (d.done && *d.done) return;
   constexpr int T = tile_lines(N, E);
   __shared__ float2 lds[N * T];
   __shared__ float2 stw[N];
-  strided_body<N, INV, E>(d, blockIdx.x, tw, lds, stw);
+  strided_body<N, INV, E>(d, (int)blockIdx.x - (red ? 1 : 0), tw, lds, stw);
 }
 
 // Many volumes with the same line length: item (volume, tile) per workgroup.
@@ -94,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_strided_batch(const StridedDes
 template <int L, int E>
 static void launch_strided_t(const StridedDesc &d, bool inv, hipStream_t st) {
   constexpr int T = tile_lines(L, E);
-  dim3 g((unsigned)((d.ncols + T - 1) / T));
+  dim3 g((unsigned)((d.ncols + T - 1) / T + (d.red.ctrl ? 1 : 0)));
   if (inv)
     hipLaunchKernelGGL((k_fft_strided<L, true, E>), g, dim3(kThreads), 0, st, d, twiddles(L));
   else
@@ -143,11 +151,11 @@ hipError_t launch_strided_batch(int L, bool inv, int v, const StridedDesc *descs
 
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
                             long estride, bool inv, int v, const int *done, hipStream_t st,
-                            long inner_valid) {
-  if (L == 1) return hipSuccess;
+                            long inner_valid, const RedArgs *red) {
+  if (L == 1) return red ? hipErrorInvalidValue : hipSuccess;
   if (!twiddles(L)) return hipErrorInvalidValue;
-  const StridedDesc d =
-      make_strided_desc(data, ncols, inner, outer_stride, estride, done, inner_valid);
+  StridedDesc d = make_strided_desc(data, ncols, inner, outer_stride, estride, done, inner_valid);
+  if (red) d.red = *red;
   switch (L) {
 #define SR3D_CASE(LL)                                                           \
   case LL:                                                                      \

@@ -52,7 +52,7 @@ struct FastDiv {
 // launch on its stream when the calling thread has profiling switched on.
 enum Stage {
   kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
-  kStStencil, kStReduce, kStSolveS, kStSetup, kStCount
+  kStStencil, kStReduce, kStSolveS, kStStencilR2c, kStSetup, kStCount
 };
 void prof_begin(int stage, hipStream_t st);
 void prof_end(hipStream_t st);
@@ -66,6 +66,16 @@ bool fft_len_supported(int n);
 // Axis kernels and their tile variants (fft_m.hip, fft_strided.hip). A
 // descriptor holds one volume's arguments; batch launches take an array of
 // descriptors and a list of (volume, tile) items, one workgroup per item.
+// Final reduction and stopping test of an iteration, run by one extra
+// workgroup of another launch (ctrl == nullptr: none).
+struct RedArgs {
+  Ctrl *ctrl;
+  const void *ps;  // stencil partials [6][nbs]
+  int nbs;
+  const void *pf;  // data-term partials [nbf]
+  int nbf;
+  int fp64;        // partials are double (else float)
+};
 struct StridedDesc {
   float2 *data;
   int ncols;
@@ -73,6 +83,7 @@ struct StridedDesc {
   int inner_valid;  // columns with (c mod inner) >= inner_valid are row padding: skipped
   long outer_stride, estride;
   const int *done;
+  RedArgs red;  // single-volume launches: a reduction run by one extra workgroup
 };
 inline StridedDesc make_strided_desc(float2 *data, long ncols, long inner, long outer_stride,
                                      long estride, const int *done, long inner_valid = -1) {
@@ -84,18 +95,9 @@ inline StridedDesc make_strided_desc(float2 *data, long ncols, long inner, long 
   d.outer_stride = outer_stride;
   d.estride = estride;
   d.done = done;
+  d.red = RedArgs{};
   return d;
 }
-// Final reduction and stopping test of an iteration, run by one extra
-// workgroup of another launch (ctrl == nullptr: none).
-struct RedArgs {
-  Ctrl *ctrl;
-  const void *ps;  // stencil partials [6][nbs]
-  int nbs;
-  const void *pf;  // data-term partials [nbf]
-  int nbf;
-  int fp64;        // partials are double (else float)
-};
 struct RowDesc {
   const float *rin;  // R2C input rows
   float2 *spec;      // half-spectrum rows (R2C output / C2R input)
@@ -124,7 +126,7 @@ hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float
                           const int *posk = nullptr, int pitch = 0);
 hipError_t launch_strided_v(float2 *data, int L, long ncols, long inner, long outer_stride,
                             long estride, bool inv, int v, const int *done, hipStream_t st,
-                            long inner_valid = -1);
+                            long inner_valid = -1, const RedArgs *red = nullptr);
 int fft_variant(int kind, int len);
 void fft_set_variant(int kind, int len, int v);
 // Times every tile variant of every axis kernel a volume S x N x M uses and
@@ -155,6 +157,10 @@ hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, 
 hipError_t fft2d_mn_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                             const int *kofp, const int *posk, int pitch, const int *done,
                             hipStream_t st);
+// The n pass alone, forward, over a spectrum whose m pass is done. With `red`
+// (N > 1), one extra workgroup runs that reduction.
+hipError_t fft_n_forward(float2 *spec, int S, int N, int M, int pitch, const int *done,
+                         hipStream_t st, const RedArgs *red = nullptr);
 
 // Fold / solve / unfold (eq. (8)-(12) and Algorithm 1 step 5a).
 struct FoldArgs {
@@ -247,6 +253,14 @@ struct StencilPlan {
 };
 StencilPlan stencil_plan(int S, int N, int M);
 hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st);
+// The stencil with the next x-update's m-axis R2C of Theta fused in
+// (stencil_r2c.hip): writes the half spectrum of Theta (positions in the
+// order kofp, rows `pitch` apart) instead of Theta. a.x and a.nu_in must be
+// non-null; the residual sums are always formed.
+bool stencil_r2c_supported(int M);
+StencilPlan stencil_r2c_plan(int S, int N, int M);
+hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *kofp, int pitch,
+                            bool fp64, hipStream_t st);
 struct BatchStencilDesc {
   AdmmStencilArgs a;
   float *nu[2];

@@ -19,45 +19,9 @@
 // reproduce the fused kernel's Theta bit for bit, which requires both to round
 // every product and sum the same way.
 #pragma clang fp contract(off)
+#include "stencil_core.h"
 
 namespace sr3d {
-
-template <typename T>
-__device__ __forceinline__ void block_reduce_n(T *v, int n, T *sh /* [n][4] */) {
-  for (int q = 0; q < n; ++q) {
-    T s = v[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    v[q] = s;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0)
-    for (int q = 0; q < n; ++q) sh[q * 4 + wid] = v[q];
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int q = 0; q < n; ++q) v[q] = sh[q * 4 + 0] + sh[q * 4 + 1] + sh[q * 4 + 2] + sh[q * 4 + 3];
-}
-
-// Workgroup b of nb is dispatched to XCD b % 8; give every XCD a contiguous
-// range of tiles so neighbouring tiles share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int x = b & 7, l = b >> 3;
-  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
-
-// Isotropic shrink (Algorithm 1 step 5b): u = a max(|a| - thr, 0) / |a|,
-// written as a max(1 - thr / |a|, 0) with the hardware reciprocal square
-// root; a = 0 gives u = 0.
-__device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr, float &u0,
-                                        float &u1, float &u2) {
-  const float n2 = a0 * a0 + a1 * a1 + a2 * a2;
-  const float s = n2 > 0.f ? fmaxf(1.f - thr * __builtin_amdgcn_rsqf(n2), 0.f) : 0.f;
-  u0 = a0 * s;
-  u1 = a1 * s;
-  u2 = a2 * s;
-}
 
 constexpr int FT_M = 64, FT_N = 8, FT_COLS = FT_M * FT_N;  // tile columns (2 per thread)
 constexpr int XR_M = FT_M + 2, XR_N = FT_N + 2, XR = XR_M * XR_N;  // x plane with ring
@@ -65,32 +29,9 @@ constexpr int FF_M = FT_M + 1, FF_N = FT_N + 1, FF = FF_M * FF_N;  // tile + low
 constexpr int NFACE = FF - FT_COLS;
 constexpr int XR_PT = (XR + kThreads - 1) / kThreads;
 
-// Quantities of one point after the update: w = u' - d', d', du = u' - u.
-struct PointQ {
-  float w[3], d[3], du[3];
-  float l[3], u[3];   // L x and u' (for the primal residual sums)
-  float nn[3];        // nu_new
-};
-
 __device__ __forceinline__ void point_update(const float *xc, const float *xn, int ri, float o0,
                                              float o1, float o2, float thr, PointQ &q) {
-  const float xi = xc[ri];
-  q.l[0] = xc[ri + 1] - xi;
-  q.l[1] = xc[ri + XR_M] - xi;
-  q.l[2] = xn[ri] - xi;
-  float uo0, uo1, uo2;
-  shrink3(o0, o1, o2, thr, uo0, uo1, uo2);
-  q.nn[0] = q.l[0] + (o0 - uo0);
-  q.nn[1] = q.l[1] + (o1 - uo1);
-  q.nn[2] = q.l[2] + (o2 - uo2);
-  shrink3(q.nn[0], q.nn[1], q.nn[2], thr, q.u[0], q.u[1], q.u[2]);
-  const float uo[3] = {uo0, uo1, uo2};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    q.d[c] = q.nn[c] - q.u[c];
-    q.w[c] = q.u[c] - q.d[c];
-    q.du[c] = q.u[c] - uo[c];
-  }
+  point_update_at(xc, xn, ri, ri + 1, ri + XR_M, o0, o1, o2, thr, q);
 }
 
 template <typename Acc, bool STATS>
@@ -321,8 +262,10 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_batch(const BatchSten
   const BatchStencilDesc d = descs[it.x];
   if (d.a.done && *d.a.done) return;
   AdmmStencilArgs a = d.a;
-  a.nu_in = d.nu[(k - 1) & 1];
-  a.nu_out = d.nu[k & 1];
+  // A select, not an index into the local copy (which would put it in scratch).
+  float *const nu0 = d.nu[0], *const nu1 = d.nu[1];
+  a.nu_in = (k & 1) ? nu0 : nu1;
+  a.nu_out = (k & 1) ? nu1 : nu0;
   stencil_body<Acc, true>(a, d.pl, it.y, it.y);
 }
 

@@ -1,0 +1,81 @@
+// Pointwise pieces of the ADMM stencil (Algorithm 1 steps 5b, 5c) shared by
+// the stencil kernels.
+//
+// Included after the file's `#pragma clang fp contract(off)`: every product
+// and sum is rounded on its own, so all kernels built from these pieces (and
+// the resume path) produce the same bits for the same point.
+#pragma once
+
+#include "sr3d_internal.h"
+
+namespace sr3d {
+
+template <typename T>
+__device__ __forceinline__ void block_reduce_n(T *v, int n, T *sh /* [n][4] */) {
+  for (int q = 0; q < n; ++q) {
+    T s = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    v[q] = s;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+    for (int q = 0; q < n; ++q) sh[q * 4 + wid] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int q = 0; q < n; ++q) v[q] = sh[q * 4 + 0] + sh[q * 4 + 1] + sh[q * 4 + 2] + sh[q * 4 + 3];
+}
+
+// Workgroup b of nb is dispatched to XCD b % 8; give every XCD a contiguous
+// range of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, l = b >> 3;
+  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Isotropic shrink (Algorithm 1 step 5b): u = a max(|a| - thr, 0) / |a|,
+// written as a max(1 - thr / |a|, 0) with the hardware reciprocal square
+// root; a = 0 gives u = 0.
+__device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr, float &u0,
+                                        float &u1, float &u2) {
+  const float n2 = a0 * a0 + a1 * a1 + a2 * a2;
+  const float s = n2 > 0.f ? fmaxf(1.f - thr * __builtin_amdgcn_rsqf(n2), 0.f) : 0.f;
+  u0 = a0 * s;
+  u1 = a1 * s;
+  u2 = a2 * s;
+}
+
+// Quantities of one point after the update: w = u' - d', d', du = u' - u.
+struct PointQ {
+  float w[3], d[3], du[3];
+  float l[3], u[3];   // L x and u' (for the primal residual sums)
+  float nn[3];        // nu_new
+};
+
+// One point of the update from x at the point (xc[ri]), at its m and n
+// successors (xc[rm], xc[rn]) and at its s successor (xn[ri]), and nu_old.
+__device__ __forceinline__ void point_update_at(const float *xc, const float *xn, int ri, int rm,
+                                                int rn, float o0, float o1, float o2, float thr,
+                                                PointQ &q) {
+  const float xi = xc[ri];
+  q.l[0] = xc[rm] - xi;
+  q.l[1] = xc[rn] - xi;
+  q.l[2] = xn[ri] - xi;
+  float uo0, uo1, uo2;
+  shrink3(o0, o1, o2, thr, uo0, uo1, uo2);
+  q.nn[0] = q.l[0] + (o0 - uo0);
+  q.nn[1] = q.l[1] + (o1 - uo1);
+  q.nn[2] = q.l[2] + (o2 - uo2);
+  shrink3(q.nn[0], q.nn[1], q.nn[2], thr, q.u[0], q.u[1], q.u[2]);
+  const float uo[3] = {uo0, uo1, uo2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q.d[c] = q.nn[c] - q.u[c];
+    q.w[c] = q.u[c] - q.d[c];
+    q.du[c] = q.u[c] - uo[c];
+  }
+}
+
+}  // namespace sr3d

@@ -1,0 +1,338 @@
+// The ADMM stencil (Algorithm 1 steps 5b, 5c and the Theta = L^T (u - d) of
+// the next step 5a) with the next x-update's first transform fused in: the
+// m-axis R2C of Theta, written straight into the x-update's spectrum layout.
+// Theta never goes to HBM, which removes 8 of the iteration's bytes per voxel
+// and one launch.
+//
+// A workgroup owns SR_ROWS whole rows along m (one wavefront per row) and
+// marches along s through a chunk of planes, as the tiled stencil does:
+//   - x of the rows n0-1 .. n0+SR_ROWS is staged in LDS (three rotating plane
+//     buffers; m wraps inside the row, so no m ring is needed);
+//   - nu_new, u', d' are formed for the tile and for row n0-1, whose
+//     n-components feed L^T at row n0; the m-neighbour values L^T needs come
+//     from the lane to the left by a cross-lane shuffle;
+//   - Theta of the plane's rows goes into the plane buffer not in use, which
+//     is then transformed along m as a half-length complex FFT and written out.
+// The pointwise arithmetic is that of the tiled stencil (stencil_core.h) and
+// the transform that of the row kernel (fft_core.h), so the spectrum matches
+// the separate stencil + R2C path bit for bit.
+#include "fft_core.h"
+#include "reduce.h"
+
+// No FMA contraction in the stencil arithmetic (see stencil_core.h); the FFT
+// helpers above never contract either.
+#pragma clang fp contract(off)
+#include "stencil_core.h"
+
+namespace sr3d {
+
+constexpr int SR_ROWS = kThreads / 64;  // rows per tile = wavefronts per workgroup
+
+template <int M>
+struct SRGeom {
+  static constexpr int CH = M / 64;                  // own points per lane and plane
+  static constexpr int H = M / 2, MH = M / 2 + 1;    // half length, half spectrum
+  static constexpr int XROWS = SR_ROWS + 2;          // x rows n0-1 .. n0+SR_ROWS
+  static constexpr int XPLANE = XROWS * M;           // floats per x plane buffer
+  static constexpr int XPT = (XPLANE + kThreads - 1) / kThreads;
+  static constexpr int FPLANE = (SR_ROWS + 1) * M;   // n-components: row n0-1 and the tile
+  static constexpr int FPT = (M + kThreads - 1) / kThreads;  // row n0-1 points per thread
+  static constexpr int TP = SR_ROWS + 1;             // FFT buffer: line pitch
+  static_assert(M % 64 == 0, "whole wavefront rows");
+  static_assert(H * TP * 2 <= XPLANE, "the FFT buffer fits one x plane buffer");
+};
+
+template <int M, typename Acc>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a, StencilPlan pl,
+                                                               float2 *__restrict__ spec,
+                                                               const int *__restrict__ kofp,
+                                                               int pitch,
+                                                               const float2 *__restrict__ twh,
+                                                               const float2 *__restrict__ twm) {
+  using G = SRGeom<M>;
+  constexpr int CH = G::CH, H = G::H, MH = G::MH, XPLANE = G::XPLANE, XPT = G::XPT;
+  constexpr int FPT = G::FPT, TP = G::TP;
+  if (a.done && *a.done) return;
+  __shared__ float xs[3][XPLANE];
+  __shared__ float fw[G::FPLANE], fd[G::FPLANE], fu[G::FPLANE];  // n-components
+  __shared__ float2 stw[H], stwm[MH];
+  __shared__ int sperm[MH];
+  __shared__ Acc sh[6 * 4];
+
+  const int b = xcd_tile(blockIdx.x, pl.blocks);
+  const int S = a.S, N = a.N;
+  const long NT = (long)S * N * M;
+  const long plane = (long)N * M;
+  const int tn = b % pl.tiles_n, ch = b / pl.tiles_n;
+  const int n0 = tn * SR_ROWS;
+  const int s0 = ch * pl.L;
+  const int s1 = min(s0 + pl.L, S);
+  const int tid = threadIdx.x, lane = tid & 63, row = tid >> 6;
+
+  stage_twiddles<H>(stw, twh);
+  for (int i = tid; i < MH; i += kThreads) {
+    stwm[i] = twm[i];
+    sperm[i] = kofp ? kofp[i] : i;
+  }
+
+  // x ring: ring row rr holds global row (n0 - 1 + rr) mod N.
+  int roff[XPT];
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const int r = tid + k * kThreads;
+    const int rr = r / M, m = r % M;
+    roff[k] = (r < XPLANE) ? ((n0 - 1 + rr) % N + N) % N * M + m : 0;
+  }
+  // Own points: row `row` of the tile, m = lane + 64 c.
+  const int gn = (n0 + row) % N;
+  const bool rval = n0 + row < N;
+  // Row n0-1 points: m = tid + kThreads j (< M).
+  const int fn = ((n0 - 1) % N + N) % N;
+
+  auto ring_fetch = [&](int sp, float *xr) {
+    const long base = (long)(((sp % S) + S) % S) * plane;
+#pragma unroll
+    for (int k = 0; k < XPT; ++k)
+      xr[k] = (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) ? a.x[base + roff[k]] : 0.f;
+  };
+  auto ring_store = [&](int buf, const float *xr) {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k)
+      if (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) xs[buf][tid + k * kThreads] = xr[k];
+  };
+  // nu_old at the own points (CH) and the row n0-1 points (FPT) of plane sp
+  auto nu_fetch = [&](int sp, float (*o)[3]) {
+    const long sb = (long)(((sp % S) + S) % S) * plane;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const long v = sb + (long)gn * M + lane + 64 * c;
+      o[c][0] = a.nu_in[v];
+      o[c][1] = a.nu_in[v + NT];
+      o[c][2] = a.nu_in[v + 2 * NT];
+    }
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int m = tid + kThreads * j;
+      const long v = sb + (long)fn * M + (m < M ? m : 0);
+      o[CH + j][0] = a.nu_in[v];
+      o[CH + j][1] = a.nu_in[v + NT];
+      o[CH + j][2] = a.nu_in[v + 2 * NT];
+    }
+  };
+  // LDS index of the point (ring row rr, m) and of its m and n successors
+  auto idx = [](int rr, int m) { return rr * M + m; };
+  auto idx_m1 = [](int rr, int m) { return rr * M + (m + 1 == M ? 0 : m + 1); };
+
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float pw[CH], pd[CH], pu[CH];  // s-components at the previous plane
+  float xr[XPT];
+  float nuc[CH + FPT][3], nun[CH + FPT][3];
+
+  // Prologue: plane s0 - 1 (its s-components feed L^T at plane s0).
+  {
+    float xa[XPT], nup[CH + FPT][3];
+    ring_fetch(s0 - 1, xa);
+    ring_fetch(s0, xr);
+    nu_fetch(s0 - 1, nup);
+    ring_store(0, xa);
+    ring_store(1, xr);
+    ring_fetch(s0 + 1, xr);
+    nu_fetch(s0, nuc);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = lane + 64 * c;
+      PointQ q;
+      point_update_at(xs[0], xs[1], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
+                      nup[c][0], nup[c][1], nup[c][2], a.thr, q);
+      pw[c] = q.w[2];
+      pd[c] = q.d[2];
+      pu[c] = q.du[2];
+    }
+  }
+
+  float2 *out = spec;
+  for (int sp = s0; sp < s1; ++sp) {
+    const int bc = (sp - s0 + 1) % 3, bn = (sp - s0 + 2) % 3, bz = (sp - s0) % 3;
+    __syncthreads();     // the previous plane's FFT buffer (buffer bn now) is read out
+    ring_store(bn, xr);  // plane sp + 1
+    if (sp + 1 < s1) {
+      ring_fetch(sp + 2, xr);
+      nu_fetch(sp + 1, nun);
+    }
+    __syncthreads();
+    const long sb = (long)sp * plane;
+    float mw[CH], md[CH], mu[CH];  // m-components at the own points
+    float sw[CH], sd[CH], su[CH], cw[CH], cd[CH], cu[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = lane + 64 * c;
+      PointQ q;
+      point_update_at(xs[bc], xs[bn], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
+                      nuc[c][0], nuc[c][1], nuc[c][2], a.thr, q);
+      const int fi = (row + 1) * M + m;
+      fw[fi] = q.w[1];
+      fd[fi] = q.d[1];
+      fu[fi] = q.du[1];
+      mw[c] = q.w[0];
+      md[c] = q.d[0];
+      mu[c] = q.du[0];
+      sw[c] = q.w[0] + q.w[1] + q.w[2];
+      sd[c] = q.d[0] + q.d[1] + q.d[2];
+      su[c] = q.du[0] + q.du[1] + q.du[2];
+      cw[c] = q.w[2];
+      cd[c] = q.d[2];
+      cu[c] = q.du[2];
+      if (rval) {
+        const long v = sb + (long)gn * M + m;
+        a.nu_out[v] = q.nn[0];
+        a.nu_out[v + NT] = q.nn[1];
+        a.nu_out[v + 2 * NT] = q.nn[2];
+        const float l2 = q.l[0] * q.l[0] + q.l[1] * q.l[1] + q.l[2] * q.l[2];
+        const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
+        acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
+        acc[1] += l2;
+        acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
+        acc[3] += l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;  // |(L x)_j|
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int m = tid + kThreads * j;
+      if (M % kThreads == 0 || m < M) {
+        PointQ q;
+        point_update_at(xs[bc], xs[bn], idx(0, m), idx_m1(0, m), idx(1, m), nuc[CH + j][0],
+                        nuc[CH + j][1], nuc[CH + j][2], a.thr, q);
+        fw[m] = q.w[1];
+        fd[m] = q.d[1];
+        fu[m] = q.du[1];
+      }
+    }
+    // The m-neighbour (m - 1, wrapping) of lane l in chunk c is lane l - 1 of
+    // chunk c, or lane 63 of chunk c - 1 for lane 0.
+    float lw[CH], ld[CH], lu[CH];
+    {
+      const int src = (lane + 63) & 63;
+      float rw[CH], rd[CH], ru[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        rw[c] = __shfl(mw[c], src);
+        rd[c] = __shfl(md[c], src);
+        ru[c] = __shfl(mu[c], src);
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int cp = (c + CH - 1) % CH;
+        lw[c] = lane ? rw[c] : rw[cp];
+        ld[c] = lane ? rd[c] : rd[cp];
+        lu[c] = lane ? ru[c] : ru[cp];
+      }
+    }
+    __syncthreads();
+    float *z = xs[bz];  // FFT buffer: z[2 (i TP + t) + e] = Theta[t][2 i + e]
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = lane + 64 * c;
+      const int fi = row * M + m;  // the point's n-neighbour (row above)
+      // (L^T z)[i] = sum_a z_a[i - e_a] - sum_a z_a[i]
+      const float ltw = lw[c] + fw[fi] + pw[c] - sw[c];
+      const float ltd = ld[c] + fd[fi] + pd[c] - sd[c];
+      const float ltu = lu[c] + fu[fi] + pu[c] - su[c];
+      z[2 * ((m >> 1) * TP + row) + (m & 1)] = ltw;
+      if (rval) {
+        acc[4] += ltu * ltu;
+        acc[5] += ltd * ltd;
+      }
+      pw[c] = cw[c];
+      pd[c] = cd[c];
+      pu[c] = cu[c];
+    }
+#pragma unroll
+    for (int k = 0; k < CH + FPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nuc[k][c] = nun[k][c];
+    __syncthreads();
+    float2 *z2 = reinterpret_cast<float2 *>(z);
+    fft_passes<H, SR_ROWS, TP, 0, 1>(z2, stw);
+    for (int w = tid; w < MH * SR_ROWS; w += kThreads) {
+      const int p = w % MH, t = w / MH;
+      if (n0 + t < N) {
+        const int k = sperm[p];
+        out[((long)sp * N + n0 + t) * pitch + p] =
+            r2c_post(z2[(k % H) * TP + t], z2[((H - k) % H) * TP + t], stwm[k]);
+      }
+    }
+  }
+  Acc acc_t[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) acc_t[q] = (Acc)acc[q];
+  block_reduce_n<Acc>(acc_t, 6, sh);
+  if (tid == 0) {
+    Acc *p = reinterpret_cast<Acc *>(a.part);
+    for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + blockIdx.x] = acc_t[q];
+  }
+}
+
+#define SR3D_STENCIL_R2C_M(X) X(64) X(128) X(192) X(256) X(384) X(512)
+
+bool stencil_r2c_supported(int M) {
+  switch (M) {
+#define SR3D_CASE(L) case L:
+    SR3D_STENCIL_R2C_M(SR3D_CASE)
+#undef SR3D_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+StencilPlan stencil_r2c_plan(int S, int N, int M) {
+  StencilPlan p;
+  p.tiles_m = 1;
+  p.tiles_n = (N + SR_ROWS - 1) / SR_ROWS;
+  // One round of workgroups over the 256 CUs at the occupancy the row
+  // length allows (registers and LDS grow with M), 2..32 planes each.
+  const long target = M <= 128 ? 1024 : M <= 256 ? 768 : 512;
+  long L = ((long)S * p.tiles_n + target - 1) / target;
+  if (L < 2) L = 2;
+  if (L > 32) L = 32;
+  if (L > S) L = S;
+  p.L = (int)L;
+  p.chunks = (S + p.L - 1) / p.L;
+  p.blocks = p.tiles_n * p.chunks;
+  return p;
+}
+
+template <int M>
+static void launch_sr(const AdmmStencilArgs &a, const StencilPlan &pl, float2 *spec,
+                      const int *kofp, int pitch, bool fp64, hipStream_t st) {
+  const float2 *twh = twiddles(M / 2), *twm = twiddles(M);
+  if (fp64)
+    hipLaunchKernelGGL((k_admm_stencil_r2c<M, double>), dim3(pl.blocks), dim3(kThreads), 0, st, a,
+                       pl, spec, kofp, pitch, twh, twm);
+  else
+    hipLaunchKernelGGL((k_admm_stencil_r2c<M, float>), dim3(pl.blocks), dim3(kThreads), 0, st, a,
+                       pl, spec, kofp, pitch, twh, twm);
+}
+
+hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *kofp, int pitch,
+                            bool fp64, hipStream_t st) {
+  if (!stencil_r2c_supported(a.M) || !a.x || !a.nu_in || !a.nu_out || !a.part || !spec ||
+      pitch < a.M / 2 + 1 || !twiddles(a.M) || !twiddles(a.M / 2))
+    return hipErrorInvalidValue;
+  const StencilPlan pl = stencil_r2c_plan(a.S, a.N, a.M);
+  prof_begin(kStStencilR2c, st);
+  switch (a.M) {
+#define SR3D_CASE(L)                                       \
+  case L:                                                  \
+    launch_sr<L>(a, pl, spec, kofp, pitch, fp64, st);      \
+    break;
+    SR3D_STENCIL_R2C_M(SR3D_CASE)
+#undef SR3D_CASE
+  }
+  const hipError_t e = hipGetLastError();
+  prof_end(st);
+  return e;
+}
+
+}  // namespace sr3d

@@ -27,6 +27,7 @@ USE_GRAPH = 0x4
 PROFILE = 0x8
 WARM_DUAL = 0x10
 UNFUSED = 0x20
+SEPARATE_R2C = 0x40
 
 
 def CHECK_INTERVAL(k):

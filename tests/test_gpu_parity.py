@@ -385,6 +385,59 @@ def test_fused_and_unfused_x_update_match_oracle(shape, rate):
     assert np.isclose(sf.objective, O.tv_objective(host(xf), y, psf, rate, LAM_TV), rtol=1e-4)
 
 
+# Row lengths the stencil with the fused m-axis R2C takes (64 .. 512), with
+# n-lengths that leave a ragged last tile of rows (n = 1, 2, 3, 6) or none.
+ROW_CASES = [
+    ((16, 6, 64), (2, 2, 2)),
+    ((24, 12, 64), (1, 3, 3)),
+    ((32, 3, 128), (2, 1, 2)),
+    ((16, 1, 256), (2, 1, 2)),
+    ((16, 2, 192), (2, 2, 2)),
+    ((16, 8, 384), (4, 2, 2)),
+    ((16, 4, 512), (2, 2, 2)),
+]
+
+
+@pytest.mark.parametrize("shape,rate", ROW_CASES)
+def test_fused_stencil_r2c_matches_separate_kernels(shape, rate):
+    """The stencil with the next x-update's m-axis R2C fused in gives the same
+    bits as the separate stencil and R2C kernels, eagerly and under graph
+    replay, and the oracle's iterate."""
+    p = phantom.make_problem(shape, rate, 1.0, 0.02, 31, n_ellipsoids=6)
+    psf = fit_psf(p["psf"], shape)
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    Y, P = dev(y), dev(psf)
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 7)
+    xf, sf = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 7)
+    xs, ss = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 7,
+                          flags=sr3d.FP64_REDUCE | sr3d.SEPARATE_R2C)
+    xg, sg = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 7,
+                          flags=sr3d.FP64_REDUCE | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(3))
+    print(f"{shape} {rate}: {O.rel_l2(host(xf), ref.x):.2e}")
+    assert torch.equal(xf, xs) and torch.equal(xf, xg)
+    assert sf.iters == ss.iters == sg.iters == 7
+    assert O.rel_l2(host(xf), ref.x) < TOL
+    # residual sums over a different tiling: equal up to FP32 summation order
+    assert np.isclose(sf.primal_rel, ss.primal_rel, rtol=1e-4)
+    assert np.isclose(sf.dual_rel, ss.dual_rel, rtol=1e-4)
+    assert np.isclose(sf.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(sf.dual_rel, ref.dual_rel, rtol=1e-3)
+
+
+def test_fused_stencil_r2c_tolerance_stop_matches_oracle():
+    """The stopping test carried by the n pass stops where the oracle does."""
+    shape, rate = (32, 32, 64), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 14)
+    tol = 2e-2
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 200, tol=tol)
+    for flags in (sr3d.FP64_REDUCE, sr3d.FP64_REDUCE | sr3d.CHECK_INTERVAL(1),
+                  sr3d.FP64_REDUCE | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(4)):
+        x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 200, tol=tol, flags=flags)
+        assert ref.converged and st.converged and abs(st.iters - ref.iters) <= 1
+        assert st.primal_rel <= tol and st.dual_rel <= tol
+        assert O.rel_l2(host(x), O.admm_tv(y, psf, rate, LAM_TV, MU, st.iters).x) < TOL
+
+
 @pytest.mark.parametrize("unfused", [False, True])
 def test_batch_mixes_fused_and_unfused_volumes(unfused):
     cases = [((8, 32, 32), (2, 2, 2)), ((32, 32, 32), (2, 2, 2)), ((16, 12, 12), (3, 4, 2)),
