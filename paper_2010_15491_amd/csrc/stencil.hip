@@ -165,7 +165,7 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
     }
     __syncthreads();
     const long sb = (long)sp * plane;
-    float sw[2], sd[2], su[2], cw[2], cd[2], cu[2];
+    float tw[2], td[2], tu[2];  // s-term minus the point's own sum
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       PointQ q;
@@ -178,12 +178,12 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
       fd[1][fi] = q.d[1];
       fu[0][fi] = q.du[0];
       fu[1][fi] = q.du[1];
-      sw[k] = q.w[0] + q.w[1] + q.w[2];
-      sd[k] = q.d[0] + q.d[1] + q.d[2];
-      su[k] = q.du[0] + q.du[1] + q.du[2];
-      cw[k] = q.w[2];
-      cd[k] = q.d[2];
-      cu[k] = q.du[2];
+      tw[k] = pw[k] - (q.w[0] + q.w[1] + q.w[2]);
+      td[k] = pd[k] - (q.d[0] + q.d[1] + q.d[2]);
+      tu[k] = pu[k] - (q.du[0] + q.du[1] + q.du[2]);
+      pw[k] = q.w[2];
+      pd[k] = q.d[2];
+      pu[k] = q.du[2];
       if (pval[k]) {
         const long v = sb + poff[k];
         a.nu_out[v] = q.nn[0];
@@ -215,10 +215,10 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int fi = (pl_ln[k] + 1) * FF_M + pl_lm[k] + 1;
-      // (L^T z)[i] = sum_a z_a[i - e_a] - sum_a z_a[i]
-      const float ltw = fw[0][fi - 1] + fw[1][fi - FF_M] + pw[k] - sw[k];
-      const float ltd = fd[0][fi - 1] + fd[1][fi - FF_M] + pd[k] - sd[k];
-      const float ltu = fu[0][fi - 1] + fu[1][fi - FF_M] + pu[k] - su[k];
+      // (L^T z)[i] = (z_m[i - e_m] + z_n[i - e_n]) + (z_s[i - e_s] - sum_a z_a[i])
+      const float ltw = (fw[0][fi - 1] + fw[1][fi - FF_M]) + tw[k];
+      const float ltd = (fd[0][fi - 1] + fd[1][fi - FF_M]) + td[k];
+      const float ltu = (fu[0][fi - 1] + fu[1][fi - FF_M]) + tu[k];
       if (pval[k]) {
         a.theta[sb + poff[k]] = ltw;
         if (STATS) {
@@ -226,9 +226,6 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
           acc[5] += ltd * ltd;
         }
       }
-      pw[k] = cw[k];
-      pd[k] = cd[k];
-      pu[k] = cu[k];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -344,7 +341,8 @@ __global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restr
     const float d = s[c] - q[c];
     nb_w[c] = q[c] - d;
   }
-  const float t = nb_w[0] + nb_w[1] + nb_w[2] - sw;
+  // (L^T w)[i] = (w_m[i - e_m] + w_n[i - e_n]) + (w_s[i - e_s] - sum_a w_a[i])
+  const float t = (nb_w[0] + nb_w[1]) + (nb_w[2] - sw);
   theta[v] = t;
 }
 

@@ -75,14 +75,29 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     sperm[i] = kofp ? kofp[i] : i;
   }
 
-  // x ring: ring row rr holds global row (n0 - 1 + rr) mod N.
-  int roff[XPT];
+  // x ring: ring row rr holds global row (n0 - 1 + rr) mod N. Element
+  // r = tid + k kThreads of a plane is (r / M, r % M); when M is a multiple of
+  // kThreads its row is the same across the workgroup, and only the row
+  // starts are kept (scalars).
+  constexpr bool kRowUniform = M % kThreads == 0;
+  int xrow[G::XROWS];
 #pragma unroll
-  for (int k = 0; k < XPT; ++k) {
-    const int r = tid + k * kThreads;
-    const int rr = r / M, m = r % M;
-    roff[k] = (r < XPLANE) ? ((n0 - 1 + rr) % N + N) % N * M + m : 0;
+  for (int rr = 0; rr < G::XROWS; ++rr) xrow[rr] = ((n0 - 1 + rr) % N + N) % N * M;
+  int roff[kRowUniform ? 1 : XPT];
+  if constexpr (!kRowUniform) {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int r = tid + k * kThreads;
+      const int rr = r / M, m = r % M;
+      roff[k] = (r < XPLANE) ? ((n0 - 1 + rr) % N + N) % N * M + m : 0;
+    }
   }
+  auto ring_off = [&](int k) {
+    if constexpr (kRowUniform)
+      return xrow[(k * kThreads) / M] + (k * kThreads) % M + tid;
+    else
+      return roff[k];
+  };
   // Own points: row `row` of the tile, m = lane + 64 c.
   const int gn = (n0 + row) % N;
   const bool rval = n0 + row < N;
@@ -93,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     const long base = (long)(((sp % S) + S) % S) * plane;
 #pragma unroll
     for (int k = 0; k < XPT; ++k)
-      xr[k] = (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) ? a.x[base + roff[k]] : 0.f;
+      xr[k] = (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) ? a.x[base + ring_off(k)] : 0.f;
   };
   auto ring_store = [&](int buf, const float *xr) {
 #pragma unroll
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     __syncthreads();
     const long sb = (long)sp * plane;
     float mw[CH], md[CH], mu[CH];  // m-components at the own points
-    float sw[CH], sd[CH], su[CH], cw[CH], cd[CH], cu[CH];
+    float tw[CH], td[CH], tu[CH];  // s-term minus the point's own sum
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int m = lane + 64 * c;
@@ -177,12 +192,12 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
       mw[c] = q.w[0];
       md[c] = q.d[0];
       mu[c] = q.du[0];
-      sw[c] = q.w[0] + q.w[1] + q.w[2];
-      sd[c] = q.d[0] + q.d[1] + q.d[2];
-      su[c] = q.du[0] + q.du[1] + q.du[2];
-      cw[c] = q.w[2];
-      cd[c] = q.d[2];
-      cu[c] = q.du[2];
+      tw[c] = pw[c] - (q.w[0] + q.w[1] + q.w[2]);
+      td[c] = pd[c] - (q.d[0] + q.d[1] + q.d[2]);
+      tu[c] = pu[c] - (q.du[0] + q.du[1] + q.du[2]);
+      pw[c] = q.w[2];
+      pd[c] = q.d[2];
+      pu[c] = q.du[2];
       if (rval) {
         const long v = sb + (long)gn * M + m;
         a.nu_out[v] = q.nn[0];
@@ -234,18 +249,15 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     for (int c = 0; c < CH; ++c) {
       const int m = lane + 64 * c;
       const int fi = row * M + m;  // the point's n-neighbour (row above)
-      // (L^T z)[i] = sum_a z_a[i - e_a] - sum_a z_a[i]
-      const float ltw = lw[c] + fw[fi] + pw[c] - sw[c];
-      const float ltd = ld[c] + fd[fi] + pd[c] - sd[c];
-      const float ltu = lu[c] + fu[fi] + pu[c] - su[c];
+      // (L^T z)[i] = (z_m[i - e_m] + z_n[i - e_n]) + (z_s[i - e_s] - sum_a z_a[i])
+      const float ltw = (lw[c] + fw[fi]) + tw[c];
+      const float ltd = (ld[c] + fd[fi]) + td[c];
+      const float ltu = (lu[c] + fu[fi]) + tu[c];
       z[2 * ((m >> 1) * TP + row) + (m & 1)] = ltw;
       if (rval) {
         acc[4] += ltu * ltu;
         acc[5] += ltd * ltd;
       }
-      pw[c] = cw[c];
-      pd[c] = cd[c];
-      pu[c] = cu[c];
     }
 #pragma unroll
     for (int k = 0; k < CH + FPT; ++k)
