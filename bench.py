@@ -132,6 +132,9 @@ def main():
                     help="tv256: the headline single-volume solve; batch64: 64 uneven volumes, "
                          "sequential single solves vs one batched solve; warm256: train the "
                          "warm-start CNN on 64^3 pairs, then plain vs warm-started solves at 256^3")
+    ap.add_argument("--separate-r2c", action="store_true",
+                    help="tv256: run the tiled stencil and the m-axis R2C as separate kernels "
+                         "(SR3D_SEPARATE_R2C) instead of the fused stencil")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a dispatch "
                          "of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -162,7 +165,8 @@ def main():
     p = sr3d._problem(hr, wl["rate"], psf, wl["lam"], wl["mu"], wl["tol"], wl["max_iter"], y=y,
                       x=x)
     ws = torch.empty(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [p]), dtype=torch.uint8, device=dev)
-    flags = sr3d.FP64_REDUCE | (0 if args.no_profile else sr3d.PROFILE)
+    base_flags = sr3d.FP64_REDUCE | (sr3d.SEPARATE_R2C if args.separate_r2c else 0)
+    flags = base_flags | (0 if args.no_profile else sr3d.PROFILE)
     flags_all = flags
     # FFT tile variants: timed once on this device, outside the timed steps.
     sr3d.autotune([(hr, wl["rate"])])
@@ -182,7 +186,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        step(sr3d.FP64_REDUCE)
+        step(base_flags)
     # Per-kernel breakdown: one untimed step with every stage timed. The timed
     # steps then carry events around the dominant kernel only (each timed
     # launch adds two event records to the stream).
@@ -244,6 +248,7 @@ def main():
                    "max_iter": wl["max_iter"], "iters": stats.iters,
                    "converged": stats.converged, "primal_rel": stats.primal_rel,
                    "dual_rel": stats.dual_rel, "reductions": "fp64",
+                   "stencil": "tiled + separate R2C" if args.separate_r2c else "fused R2C",
                    "fft_tiles_kind_len_variant": fft_tiles,
                    "parallelism": "single_gpu"},
         "roofline": roofline,
