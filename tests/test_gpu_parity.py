@@ -484,3 +484,13 @@ def test_full_size_256_first_iterations_and_invariants():
     assert np.isfinite(st.objective) and st.iters >= 1
     print(f"256^3 stop: iters {st.iters} converged {st.converged} "
           f"primal {st.primal_rel:.3e} dual {st.dual_rel:.3e}")
+    # the benchmark's kernels (stencil with the fused R2C, fused x-update)
+    # against the separate stencil + R2C and the unfused x-update
+    xf, sf = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5)
+    xs, ss = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, flags=sr3d.FP64_REDUCE | sr3d.SEPARATE_R2C)
+    xu, su = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, flags=sr3d.FP64_REDUCE | sr3d.UNFUSED)
+    assert torch.equal(xf, xs)
+    assert O.rel_l2(host(xf), host(xu)) < 1e-6
+    for a_, b_ in ((sf, ss), (sf, su)):
+        assert np.isclose(a_.primal_rel, b_.primal_rel, rtol=1e-4)
+        assert np.isclose(a_.dual_rel, b_.dual_rel, rtol=1e-4)
