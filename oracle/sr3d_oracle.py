@@ -40,7 +40,7 @@ import scipy.fft as sfft
 __all__ = [
     "WORKERS", "hr_shape_of", "lr_shape_of", "psf_to_otf", "blur", "blur_adjoint",
     "decimate", "zero_fill", "degrade", "fold", "unfold", "diff_symbol_sq",
-    "grad", "grad_adjoint", "shrink", "tikhonov", "tikhonov_objective",
+    "grad", "grad_adjoint", "shrink", "shrink_aniso", "tikhonov", "tikhonov_objective",
     "x_update", "AdmmResult", "admm_tv", "min_norm_dual", "tv_objective", "data_term", "psnr",
     "rel_l2",
 ]
@@ -205,6 +205,14 @@ def shrink(nu, thr):
     return nu * scale[None]
 
 
+def shrink_aniso(nu, thr):
+    """Anisotropic TV, sum_j sum_a |(Lx)_{j,a}|: one of the other regularisers
+    the same x-step serves (Sec. III-B). Step 5b becomes the proximal map of
+    thr ||.||_1, a soft threshold of every component on its own:
+    sign(nu) max{0, |nu| - thr}."""
+    return np.sign(nu) * np.maximum(0.0, np.abs(nu) - thr)
+
+
 # ---------------------------------------------------------------------------
 # Tikhonov closed form, Sec. III-A, eq. (5)-(12)
 # ---------------------------------------------------------------------------
@@ -288,10 +296,13 @@ def data_term(x, y, otf, rate):
     return 0.5 * float(np.sum(r * r))
 
 
-def tv_objective(x, y, psf, rate, lam):
-    """Eq. (3) with isotropic TV: 1/2||y - DHx||^2 + lam sum_j ||(Lx)_j||_2."""
+def tv_objective(x, y, psf, rate, lam, aniso=False):
+    """Eq. (3) with isotropic TV: 1/2||y - DHx||^2 + lam sum_j ||(Lx)_j||_2;
+    with ``aniso`` the anisotropic TV lam sum_j ||(Lx)_j||_1."""
     otf = psf_to_otf(psf, x.shape)
     g = grad(x)
+    if aniso:
+        return data_term(x, y, otf, rate) + lam * float(np.sum(np.abs(g)))
     return data_term(x, y, otf, rate) + lam * float(np.sum(np.sqrt(np.sum(g * g, axis=0))))
 
 
@@ -325,8 +336,10 @@ def min_norm_dual(x0, y, psf, rate, mu):
 
 
 def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
-            callback=None, warm_dual=False, tol_dual=None):
-    """3D-FSR-l2-TV (Algorithm 1).
+            callback=None, warm_dual=False, tol_dual=None, aniso=False):
+    """3D-FSR-l2-TV (Algorithm 1). With ``aniso`` the regulariser is the
+    anisotropic TV and step 5b the per-component soft threshold
+    (``shrink_aniso``); every other step is unchanged.
 
     Inputs y, H (through ``psf``), lam, r = prod(rate), mu.
     Initialisation: x0 (zero if None); nu = L x0 (with d = 0), u0 = shrink(nu),
@@ -346,12 +359,13 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
     G = diff_symbol_sq(hr)
     FDty = np.conj(otf) * _fftn(zero_fill(y, rate))
     thr = lam / mu
+    prox = shrink_aniso if aniso else shrink
 
     x = np.zeros(hr) if x0 is None else np.asarray(x0, np.float64).copy()
     nu = grad(x)
     if x0 is not None and warm_dual:
         nu = nu + min_norm_dual(x, y, psf, rate, mu)
-    u = shrink(nu, thr)
+    u = prox(nu, thr)
     d = nu - u
 
     hist = []
@@ -365,7 +379,7 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
         x = np.real(_ifftn(x_update(Fk, otf, G, mu, rate)))
         Lx = grad(x)
         nu = Lx + d
-        u_new = shrink(nu, thr)
+        u_new = prox(nu, thr)
         d_new = d + (Lx - u_new)
 
         r_norm = float(np.sqrt(np.sum((Lx - u_new) ** 2)))

@@ -386,6 +386,70 @@ def test_admm_reaches_tv_minimiser_kkt():
         assert O.tv_objective(x + 1e-2 * rng.standard_normal(x.shape), y, psf, rate, lam) >= f0
 
 
+def test_aniso_shrink_is_the_componentwise_proximal_map():
+    """u = argmin thr ||u||_1 + 1/2 ||u - nu||^2, component by component: the
+    minimiser of the scalar problem found by brute force on a fine grid."""
+    rng = np.random.default_rng(15)
+    thr = 0.3
+    nu = rng.standard_normal((3, 60)) * rng.uniform(0, 1.5, 60)[None]
+    nu[:, 0] = 0.0
+    nu[:, 1] = [thr, -thr, 0.5 * thr]
+    u = O.shrink_aniso(nu, thr)
+    assert np.all(u[np.abs(nu) <= thr] == 0.0)
+    grid = np.linspace(-3.0, 3.0, 600001)
+    for v, w in zip(nu.ravel(), u.ravel()):
+        f = thr * np.abs(grid) + 0.5 * (grid - v) ** 2
+        assert abs(grid[np.argmin(f)] - w) <= 1e-5
+    # differs from the isotropic map whenever two components are non-zero
+    assert np.abs(u[:, 2:] - O.shrink(nu, thr)[:, 2:]).max() > 1e-2
+
+
+def test_aniso_equals_iso_when_only_one_axis_varies():
+    """With no decimation along n and s the problem is invariant under shifts
+    along them, so data constant along n and s keep every iterate constant
+    along them: only the m-component of L x is non-zero and both shrinks agree."""
+    rng = np.random.default_rng(16)
+    shape, rate = (8, 8, 16), (2, 1, 1)
+    y1 = rng.standard_normal(shape[2] // rate[0])
+    y = np.broadcast_to(y1, O.lr_shape_of(shape, rate)).copy()
+    psf = rand_psf(rng, (3, 3, 3))
+    a = O.admm_tv(y, psf, rate, 0.02, 0.1, 25)
+    b = O.admm_tv(y, psf, rate, 0.02, 0.1, 25, aniso=True)
+    assert np.abs(a.x - b.x).max() < 1e-12 * np.abs(a.x).max()
+    assert np.abs(O.grad(a.x)[1:]).max() < 1e-12 * np.abs(a.x).max()
+    assert np.isclose(O.tv_objective(a.x, y, psf, rate, 0.02),
+                      O.tv_objective(a.x, y, psf, rate, 0.02, aniso=True), rtol=1e-12)
+
+
+def test_aniso_admm_reaches_minimiser_kkt():
+    """KKT conditions of the anisotropic TV problem after 3000 iterations at
+    8^3: H^T D^T (DHx - y) + lam L^T z = 0 with z = (mu/lam) d, |z_a| <= 1 per
+    component and z_a = sign(u_a) where u_a != 0, Lx = u; no nearby point has
+    a lower anisotropic objective, and the minimiser is not the isotropic one."""
+    y, psf, rate = _toy_problem(seed=25)
+    lam, mu = 1e-3, 0.2
+    res = O.admm_tv(y, psf, rate, lam, mu, 3000, record=True, aniso=True)
+    assert res.history[-1][0] < 1e-5 and res.history[-1][1] < 1e-6
+    x, u, d = res.x, res.u, res.d
+    z = (mu / lam) * d
+    r = O.zero_fill(O.decimate(conv_wrap(x, psf), rate) - y, rate)
+    stat = corr_wrap(r, psf) + lam * O.grad_adjoint(z)
+    scale = np.abs(corr_wrap(O.zero_fill(y, rate), psf)).max()
+    assert np.abs(stat).max() < 1e-6 * scale
+    assert np.abs(O.grad(x) - u).max() < 1e-5 * np.abs(u).max()
+    assert np.abs(z).max() <= 1 + 1e-9
+    on = np.abs(u) > 1e-6
+    assert np.allclose(z[on], np.sign(u[on]), atol=1e-6)
+    assert np.ptp(x) > 0.1
+    f0 = O.tv_objective(x, y, psf, rate, lam, aniso=True)
+    rng = np.random.default_rng(1)
+    for _ in range(8):
+        assert O.tv_objective(x + 1e-2 * rng.standard_normal(x.shape), y, psf, rate, lam,
+                              aniso=True) >= f0
+    iso = O.admm_tv(y, psf, rate, lam, mu, 3000)
+    assert O.rel_l2(iso.x, x) > 1e-4
+
+
 def test_admm_large_lambda_gives_constant():
     """lam above the TV kink: the minimiser is the constant mean(y)/Lambda(0)."""
     y, psf, rate = _toy_problem(seed=23)
