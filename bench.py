@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--separate-r2c", action="store_true",
                     help="tv256: run the tiled stencil and the m-axis R2C as separate kernels "
                          "(SR3D_SEPARATE_R2C) instead of the fused stencil")
+    ap.add_argument("--aniso", action="store_true",
+                    help="tv256: anisotropic TV (SR3D_TV_ANISO) instead of the isotropic default")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a dispatch "
                          "of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -165,7 +167,8 @@ def main():
     p = sr3d._problem(hr, wl["rate"], psf, wl["lam"], wl["mu"], wl["tol"], wl["max_iter"], y=y,
                       x=x)
     ws = torch.empty(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [p]), dtype=torch.uint8, device=dev)
-    base_flags = sr3d.FP64_REDUCE | (sr3d.SEPARATE_R2C if args.separate_r2c else 0)
+    base_flags = (sr3d.FP64_REDUCE | (sr3d.SEPARATE_R2C if args.separate_r2c else 0)
+                  | (sr3d.TV_ANISO if args.aniso else 0))
     flags = base_flags | (0 if args.no_profile else sr3d.PROFILE)
     flags_all = flags
     # FFT tile variants: timed once on this device, outside the timed steps.
@@ -249,6 +252,7 @@ def main():
                    "converged": stats.converged, "primal_rel": stats.primal_rel,
                    "dual_rel": stats.dual_rel, "reductions": "fp64",
                    "stencil": "tiled + separate R2C" if args.separate_r2c else "fused R2C",
+                   "regulariser": "anisotropic TV" if args.aniso else "isotropic TV",
                    "fft_tiles_kind_len_variant": fft_tiles,
                    "parallelism": "single_gpu"},
         "roofline": roofline,

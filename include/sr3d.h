@@ -104,6 +104,11 @@ typedef struct {
                                   R2C of the next x-update as separate kernels even where the
                                   row length admits the fused stencil (64, 128, 192, 256,
                                   384, 512); same bits, for testing */
+#define SR3D_TV_ANISO    0x80  /* anisotropic TV, lambda sum_j ||(L x)_j||_1, instead of the
+                                  isotropic sum_j ||(L x)_j||_2: one of the other regularisers
+                                  the same x-step serves (Sec. III-B). Step 5b becomes a soft
+                                  threshold of every component; the objective reports the l1
+                                  form. Every other step is unchanged. */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */

@@ -187,6 +187,7 @@ struct TvWs {
   int nbStile, nbSrow;  // stencil workgroups: tiled kernel, fused stencil + R2C kernel
   bool fused;  // this solve uses the fused x-update (set by the caller)
   bool fsten;  // ... and the stencil with the m-axis R2C fused in
+  bool aniso;  // anisotropic TV (SR3D_TV_ANISO)
 };
 
 // Workspace of one TV solve. nu[0] is only used when the caller passes no
@@ -234,6 +235,7 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->fused = g.sp.fused && !(flags & SR3D_UNFUSED);
   L->nbF = L->fused ? L->nbFused : L->nbFold;
   L->fsten = L->fused && L->nbSrow > 0 && !(flags & SR3D_SEPARATE_R2C);
+  L->aniso = (flags & SR3D_TV_ANISO) != 0;
   L->nbS = L->fsten ? L->nbSrow : L->nbStile;
 }
 
@@ -355,7 +357,7 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   }
   const float thr = p->lambda_tv / p->mu;
   if (flags & SR3D_RESUME) {
-    if ((e = theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, st))) return e;
+    if ((e = theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, L.aniso, st))) return e;
     return theta0_spectrum(g, L, st);
   }
   const float *xinit = p->x0;
@@ -375,6 +377,7 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   AdmmStencilArgs sa{};
   sa.x = xinit; sa.nu_in = nullptr; sa.nu_out = nu0; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = thr; sa.part = nullptr; sa.done = nullptr;
+  sa.aniso = L.aniso ? 1 : 0;
   if ((e = admm_stencil(sa, false, false, st))) return e;
   return theta0_spectrum(g, L, st);
 }
@@ -420,7 +423,7 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
   AdmmStencilArgs sa{};
   sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
-  sa.part = L.partS; sa.done = done;
+  sa.part = L.partS; sa.done = done; sa.aniso = L.aniso ? 1 : 0;
   if (L.fsten)
     e = admm_stencil_r2c(sa, L.w, L.tab, g.sp.pitch, fp64, st);
   else
@@ -715,7 +718,8 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
   for (auto &gr : plan.groups) {
     if (gr.kind != 7) continue;
     prof_begin(kStStencil, st);
-    e = admm_stencil_batch(H.sten, items_of(gr), (int)gr.items.size(), k, fp64, st);
+    // the flags, and so the regulariser, are the same for every volume
+    e = admm_stencil_batch(H.sten, items_of(gr), (int)gr.items.size(), k, fp64, Ls[0].aniso, st);
     prof_end(st);
     if (e) return e;
   }
@@ -789,7 +793,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     BatchStencilDesc sd{};
     sd.a.x = p[v].x; sd.a.theta = L.theta;
     sd.a.S = G.S; sd.a.N = G.N; sd.a.M = G.M; sd.a.thr = p[v].lambda_tv / p[v].mu;
-    sd.a.part = L.partS; sd.a.done = done;
+    sd.a.part = L.partS; sd.a.done = done; sd.a.aniso = L.aniso ? 1 : 0;
     sd.nu[0] = nu0[v];
     sd.nu[1] = L.nu[1];
     sd.pl = stencil_plan(G.S, G.N, G.M);

@@ -247,6 +247,7 @@ struct AdmmStencilArgs {
   float thr;           // lambda / mu
   void *part;          // [6][blocks]: |Lx-u'|^2, |Lx|^2, |u'|^2, sum|(Lx)_j|, |L^T(u'-u)|^2, |L^T d'|^2
   const int *done;
+  int aniso;           // anisotropic TV: per-component shrink, |(Lx)_j|_1 in the objective
 };
 struct StencilPlan {
   int tiles_m, tiles_n, chunks, L, blocks;
@@ -267,9 +268,9 @@ struct BatchStencilDesc {
   StencilPlan pl;
 };
 hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
-                              bool fp64, hipStream_t st);
+                              bool fp64, bool aniso, hipStream_t st);
 hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,
-                         hipStream_t st);
+                         bool aniso, hipStream_t st);
 // Final reduction of the partial sums and the stopping test.
 hipError_t reduce_and_test(Ctrl *ctrl, const void *partS, int nbS, const void *partF, int nbF,
                            bool fp64, hipStream_t st);

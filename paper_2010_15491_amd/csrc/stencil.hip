@@ -29,12 +29,13 @@ constexpr int FF_M = FT_M + 1, FF_N = FT_N + 1, FF = FF_M * FF_N;  // tile + low
 constexpr int NFACE = FF - FT_COLS;
 constexpr int XR_PT = (XR + kThreads - 1) / kThreads;
 
+template <bool ANISO>
 __device__ __forceinline__ void point_update(const float *xc, const float *xn, int ri, float o0,
                                              float o1, float o2, float thr, PointQ &q) {
-  point_update_at(xc, xn, ri, ri + 1, ri + XR_M, o0, o1, o2, thr, q);
+  point_update_at<ANISO>(xc, xn, ri, ri + 1, ri + XR_M, o0, o1, o2, thr, q);
 }
 
-template <typename Acc, bool STATS>
+template <typename Acc, bool STATS, bool ANISO>
 __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const StencilPlan &pl, int b,
                                              int slot) {
   __shared__ float xs[3][XR];
@@ -148,7 +149,7 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       PointQ q;
-      point_update(xs[0], xs[1], (pl_ln[k] + 1) * XR_M + pl_lm[k] + 1, nup[k][0], nup[k][1],
+      point_update<ANISO>(xs[0], xs[1], (pl_ln[k] + 1) * XR_M + pl_lm[k] + 1, nup[k][0], nup[k][1],
                    nup[k][2], a.thr, q);
       pw[k] = q.w[2];
       pd[k] = q.d[2];
@@ -170,7 +171,7 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
     for (int k = 0; k < 2; ++k) {
       PointQ q;
       const int ri = (pl_ln[k] + 1) * XR_M + pl_lm[k] + 1;
-      point_update(xs[bc], xs[bn], ri, nuc[k][0], nuc[k][1], nuc[k][2], a.thr, q);
+      point_update<ANISO>(xs[bc], xs[bn], ri, nuc[k][0], nuc[k][1], nuc[k][2], a.thr, q);
       const int fi = (pl_ln[k] + 1) * FF_M + pl_lm[k] + 1;
       fw[0][fi] = q.w[0];
       fw[1][fi] = q.w[1];
@@ -195,13 +196,13 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
           acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
           acc[1] += l2;
           acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-          acc[3] += l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;  // |(L x)_j|
+          acc[3] += tv_term<ANISO>(q.l);  // |(L x)_j|
         }
       }
     }
     if (has_face) {
       PointQ q;
-      point_update(xs[bc], xs[bn], (f_ln + 1) * XR_M + f_lm + 1, nuc[2][0], nuc[2][1], nuc[2][2],
+      point_update<ANISO>(xs[bc], xs[bn], (f_ln + 1) * XR_M + f_lm + 1, nuc[2][0], nuc[2][1], nuc[2][2],
                    a.thr, q);
       const int fi = (f_ln + 1) * FF_M + f_lm + 1;
       fw[0][fi] = q.w[0];
@@ -244,14 +245,14 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
   }
 }
 
-template <typename Acc, bool STATS>
+template <typename Acc, bool STATS, bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_admm_stencil(AdmmStencilArgs a, StencilPlan pl) {
   if (a.done && *a.done) return;
-  stencil_body<Acc, STATS>(a, pl, xcd_tile(blockIdx.x, pl.blocks), blockIdx.x);
+  stencil_body<Acc, STATS, ANISO>(a, pl, xcd_tile(blockIdx.x, pl.blocks), blockIdx.x);
 }
 
 // Batch: item (volume, tile); iteration k reads nu[(k-1)&1] and writes nu[k&1].
-template <typename Acc>
+template <typename Acc, bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_admm_stencil_batch(const BatchStencilDesc *__restrict__ descs,
                                                                  const int2 *__restrict__ items,
                                                                  int k) {
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_batch(const BatchSten
   float *const nu0 = d.nu[0], *const nu1 = d.nu[1];
   a.nu_in = (k & 1) ? nu0 : nu1;
   a.nu_out = (k & 1) ? nu1 : nu0;
-  stencil_body<Acc, true>(a, d.pl, it.y, it.y);
+  stencil_body<Acc, true, ANISO>(a, d.pl, it.y, it.y);
 }
 
 StencilPlan stencil_plan(int S, int N, int M) {
@@ -283,34 +284,49 @@ StencilPlan stencil_plan(int S, int N, int M) {
   return p;
 }
 
-hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
-                              bool fp64, hipStream_t st) {
-  if (nitems == 0) return hipSuccess;
+template <bool ANISO>
+static void launch_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems,
+                                 int k, bool fp64, hipStream_t st) {
   if (fp64)
-    hipLaunchKernelGGL((k_admm_stencil_batch<double>), dim3(nitems), dim3(kThreads), 0, st, descs,
-                       items, k);
+    hipLaunchKernelGGL((k_admm_stencil_batch<double, ANISO>), dim3(nitems), dim3(kThreads), 0, st,
+                       descs, items, k);
   else
-    hipLaunchKernelGGL((k_admm_stencil_batch<float>), dim3(nitems), dim3(kThreads), 0, st, descs,
-                       items, k);
+    hipLaunchKernelGGL((k_admm_stencil_batch<float, ANISO>), dim3(nitems), dim3(kThreads), 0, st,
+                       descs, items, k);
+}
+
+hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
+                              bool fp64, bool aniso, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  if (aniso) launch_stencil_batch<true>(descs, items, nitems, k, fp64, st);
+  else launch_stencil_batch<false>(descs, items, nitems, k, fp64, st);
   return hipGetLastError();
+}
+
+template <bool ANISO>
+static void launch_stencil(const AdmmStencilArgs &a, const StencilPlan &pl, bool stats, bool fp64,
+                           hipStream_t st) {
+  dim3 g(pl.blocks), b(kThreads);
+  if (stats) {
+    if (fp64) hipLaunchKernelGGL((k_admm_stencil<double, true, ANISO>), g, b, 0, st, a, pl);
+    else hipLaunchKernelGGL((k_admm_stencil<float, true, ANISO>), g, b, 0, st, a, pl);
+  } else {
+    hipLaunchKernelGGL((k_admm_stencil<float, false, ANISO>), g, b, 0, st, a, pl);
+  }
 }
 
 hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStream_t st) {
   const StencilPlan pl = stencil_plan(a.S, a.N, a.M);
-  dim3 g(pl.blocks), b(kThreads);
   prof_begin(kStStencil, st);
-  if (stats) {
-    if (fp64) hipLaunchKernelGGL((k_admm_stencil<double, true>), g, b, 0, st, a, pl);
-    else hipLaunchKernelGGL((k_admm_stencil<float, true>), g, b, 0, st, a, pl);
-  } else {
-    hipLaunchKernelGGL((k_admm_stencil<float, false>), g, b, 0, st, a, pl);
-  }
+  if (a.aniso) launch_stencil<true>(a, pl, stats, fp64, st);
+  else launch_stencil<false>(a, pl, stats, fp64, st);
   hipError_t e = hipGetLastError();
   prof_end(st);
   return e;
 }
 
 // Theta = L^T (u - d) of a given state nu (resuming from a checkpoint).
+template <bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restrict__ nu,
                                                             float *__restrict__ theta, int S, int N,
                                                             int M, float thr) {
@@ -328,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restr
   // iteration bit for bit.
   float u[3], w[3], nb_w[3];
   const float p[3] = {nu[v], nu[v + NT], nu[v + 2 * NT]};
-  shrink3(p[0], p[1], p[2], thr, u[0], u[1], u[2]);
+  shrink_tv<ANISO>(p[0], p[1], p[2], thr, u[0], u[1], u[2]);
   for (int c = 0; c < 3; ++c) {
     const float d = p[c] - u[c];
     w[c] = u[c] - d;
@@ -337,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restr
   for (int c = 0; c < 3; ++c) {
     float q[3];
     const float s[3] = {nu[nb[c]], nu[nb[c] + NT], nu[nb[c] + 2 * NT]};
-    shrink3(s[0], s[1], s[2], thr, q[0], q[1], q[2]);
+    shrink_tv<ANISO>(s[0], s[1], s[2], thr, q[0], q[1], q[2]);
     const float d = s[c] - q[c];
     nb_w[c] = q[c] - d;
   }
@@ -347,10 +363,13 @@ __global__ __launch_bounds__(kThreads) void k_theta_from_nu(const float *__restr
 }
 
 hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,
-                         hipStream_t st) {
+                         bool aniso, hipStream_t st) {
   const long NT = (long)S * N * M;
-  hipLaunchKernelGGL(k_theta_from_nu, dim3((unsigned)((NT + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, st, nu, theta, S, N, M, thr);
+  const dim3 g((unsigned)((NT + kThreads - 1) / kThreads));
+  if (aniso)
+    hipLaunchKernelGGL(k_theta_from_nu<true>, g, dim3(kThreads), 0, st, nu, theta, S, N, M, thr);
+  else
+    hipLaunchKernelGGL(k_theta_from_nu<false>, g, dim3(kThreads), 0, st, nu, theta, S, N, M, thr);
   return hipGetLastError();
 }
 

@@ -47,6 +47,37 @@ __device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr,
   u2 = a2 * s;
 }
 
+// Anisotropic TV (sum over voxels and components of |(L x)_{j,a}|, one of the
+// other regularisers the same x-step serves, Sec. III-B): step 5b becomes the
+// soft threshold of every component, u = sign(a) max(|a| - thr, 0).
+__device__ __forceinline__ float shrink1(float a, float thr) {
+  return copysignf(fmaxf(fabsf(a) - thr, 0.f), a);
+}
+
+template <bool ANISO>
+__device__ __forceinline__ void shrink_tv(float a0, float a1, float a2, float thr, float &u0,
+                                          float &u1, float &u2) {
+  if constexpr (ANISO) {
+    u0 = shrink1(a0, thr);
+    u1 = shrink1(a1, thr);
+    u2 = shrink1(a2, thr);
+  } else {
+    shrink3(a0, a1, a2, thr, u0, u1, u2);
+  }
+}
+
+// The regulariser's term of one voxel from (L x)_j: ||.||_2 (isotropic) or
+// ||.||_1 (anisotropic).
+template <bool ANISO>
+__device__ __forceinline__ float tv_term(const float *l) {
+  if constexpr (ANISO) {
+    return fabsf(l[0]) + fabsf(l[1]) + fabsf(l[2]);
+  } else {
+    const float l2 = l[0] * l[0] + l[1] * l[1] + l[2] * l[2];
+    return l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;
+  }
+}
+
 // Quantities of one point after the update: w = u' - d', d', du = u' - u.
 struct PointQ {
   float w[3], d[3], du[3];
@@ -56,6 +87,7 @@ struct PointQ {
 
 // One point of the update from x at the point (xc[ri]), at its m and n
 // successors (xc[rm], xc[rn]) and at its s successor (xn[ri]), and nu_old.
+template <bool ANISO>
 __device__ __forceinline__ void point_update_at(const float *xc, const float *xn, int ri, int rm,
                                                 int rn, float o0, float o1, float o2, float thr,
                                                 PointQ &q) {
@@ -64,11 +96,11 @@ __device__ __forceinline__ void point_update_at(const float *xc, const float *xn
   q.l[1] = xc[rn] - xi;
   q.l[2] = xn[ri] - xi;
   float uo0, uo1, uo2;
-  shrink3(o0, o1, o2, thr, uo0, uo1, uo2);
+  shrink_tv<ANISO>(o0, o1, o2, thr, uo0, uo1, uo2);
   q.nn[0] = q.l[0] + (o0 - uo0);
   q.nn[1] = q.l[1] + (o1 - uo1);
   q.nn[2] = q.l[2] + (o2 - uo2);
-  shrink3(q.nn[0], q.nn[1], q.nn[2], thr, q.u[0], q.u[1], q.u[2]);
+  shrink_tv<ANISO>(q.nn[0], q.nn[1], q.nn[2], thr, q.u[0], q.u[1], q.u[2]);
   const float uo[3] = {uo0, uo1, uo2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

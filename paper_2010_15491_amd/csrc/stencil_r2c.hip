@@ -42,7 +42,7 @@ struct SRGeom {
   static_assert(H * TP * 2 <= XPLANE, "the FFT buffer fits one x plane buffer");
 };
 
-template <int M, typename Acc>
+template <int M, typename Acc, bool ANISO>
 __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a, StencilPlan pl,
                                                                float2 *__restrict__ spec,
                                                                const int *__restrict__ kofp,
@@ -158,8 +158,8 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     for (int c = 0; c < CH; ++c) {
       const int m = lane + 64 * c;
       PointQ q;
-      point_update_at(xs[0], xs[1], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
-                      nup[c][0], nup[c][1], nup[c][2], a.thr, q);
+      point_update_at<ANISO>(xs[0], xs[1], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
+                             nup[c][0], nup[c][1], nup[c][2], a.thr, q);
       pw[c] = q.w[2];
       pd[c] = q.d[2];
       pu[c] = q.du[2];
@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
     for (int c = 0; c < CH; ++c) {
       const int m = lane + 64 * c;
       PointQ q;
-      point_update_at(xs[bc], xs[bn], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
-                      nuc[c][0], nuc[c][1], nuc[c][2], a.thr, q);
+      point_update_at<ANISO>(xs[bc], xs[bn], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
+                             nuc[c][0], nuc[c][1], nuc[c][2], a.thr, q);
       const int fi = (row + 1) * M + m;
       fw[fi] = q.w[1];
       fd[fi] = q.d[1];
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
         acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
         acc[1] += l2;
         acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-        acc[3] += l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;  // |(L x)_j|
+        acc[3] += tv_term<ANISO>(q.l);  // |(L x)_j|
       }
     }
 #pragma unroll
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
       const int m = tid + kThreads * j;
       if (M % kThreads == 0 || m < M) {
         PointQ q;
-        point_update_at(xs[bc], xs[bn], idx(0, m), idx_m1(0, m), idx(1, m), nuc[CH + j][0],
-                        nuc[CH + j][1], nuc[CH + j][2], a.thr, q);
+        point_update_at<ANISO>(xs[bc], xs[bn], idx(0, m), idx_m1(0, m), idx(1, m),
+                               nuc[CH + j][0], nuc[CH + j][1], nuc[CH + j][2], a.thr, q);
         fw[m] = q.w[1];
         fd[m] = q.d[1];
         fu[m] = q.du[1];
@@ -315,16 +315,23 @@ StencilPlan stencil_r2c_plan(int S, int N, int M) {
   return p;
 }
 
+template <int M, bool ANISO>
+static void launch_sr_t(const AdmmStencilArgs &a, const StencilPlan &pl, float2 *spec,
+                        const int *kofp, int pitch, bool fp64, hipStream_t st) {
+  const float2 *twh = twiddles(M / 2), *twm = twiddles(M);
+  if (fp64)
+    hipLaunchKernelGGL((k_admm_stencil_r2c<M, double, ANISO>), dim3(pl.blocks), dim3(kThreads), 0,
+                       st, a, pl, spec, kofp, pitch, twh, twm);
+  else
+    hipLaunchKernelGGL((k_admm_stencil_r2c<M, float, ANISO>), dim3(pl.blocks), dim3(kThreads), 0,
+                       st, a, pl, spec, kofp, pitch, twh, twm);
+}
+
 template <int M>
 static void launch_sr(const AdmmStencilArgs &a, const StencilPlan &pl, float2 *spec,
                       const int *kofp, int pitch, bool fp64, hipStream_t st) {
-  const float2 *twh = twiddles(M / 2), *twm = twiddles(M);
-  if (fp64)
-    hipLaunchKernelGGL((k_admm_stencil_r2c<M, double>), dim3(pl.blocks), dim3(kThreads), 0, st, a,
-                       pl, spec, kofp, pitch, twh, twm);
-  else
-    hipLaunchKernelGGL((k_admm_stencil_r2c<M, float>), dim3(pl.blocks), dim3(kThreads), 0, st, a,
-                       pl, spec, kofp, pitch, twh, twm);
+  if (a.aniso) launch_sr_t<M, true>(a, pl, spec, kofp, pitch, fp64, st);
+  else launch_sr_t<M, false>(a, pl, spec, kofp, pitch, fp64, st);
 }
 
 hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *kofp, int pitch,

@@ -28,6 +28,7 @@ PROFILE = 0x8
 WARM_DUAL = 0x10
 UNFUSED = 0x20
 SEPARATE_R2C = 0x40
+TV_ANISO = 0x80
 
 
 def CHECK_INTERVAL(k):

@@ -438,6 +438,73 @@ def test_fused_stencil_r2c_tolerance_stop_matches_oracle():
         assert O.rel_l2(host(x), O.admm_tv(y, psf, rate, LAM_TV, MU, st.iters).x) < TOL
 
 
+# Anisotropic TV through the same x-step: fused stencil (m = 64, 128), tiled
+# stencil (m = 32, 24 and SR3D_SEPARATE_R2C), unfused x-update.
+ANISO_CASES = [
+    ((32, 32, 32), (2, 2, 2), 0),
+    ((16, 6, 64), (2, 2, 2), 0),
+    ((32, 3, 128), (2, 1, 2), 0),
+    ((32, 32, 64), (2, 2, 2), 0x40),
+    ((24, 12, 24), (1, 3, 3), 0x20),
+]
+
+
+@pytest.mark.parametrize("shape,rate,extra", ANISO_CASES)
+def test_tv_aniso_matches_oracle(shape, rate, extra):
+    p = phantom.make_problem(shape, rate, 1.0, 0.02, 41, n_ellipsoids=6)
+    psf = fit_psf(p["psf"], shape)
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 10, aniso=True)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10,
+                         flags=sr3d.FP64_REDUCE | sr3d.TV_ANISO | extra)
+    err = O.rel_l2(host(x), ref.x)
+    print(f"{shape} {rate} flags+{extra:#x}: aniso rel-L2 {err:.2e}")
+    assert err < TOL
+    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
+    assert np.isclose(st.objective, O.tv_objective(host(x), y, psf, rate, LAM_TV, aniso=True),
+                      rtol=1e-4)
+    iso = O.admm_tv(y, psf, rate, LAM_TV, MU, 10)
+    assert O.rel_l2(iso.x, ref.x) > 100 * TOL  # the two regularisers really differ here
+
+
+def test_tv_aniso_paths_agree_bitwise_and_resume():
+    shape, rate = (32, 32, 64), (2, 2, 2)
+    y, psf, _ = problem(shape, rate, 1.5, 0.02, 42)
+    Y, P = dev(y), dev(psf)
+    fl = sr3d.FP64_REDUCE | sr3d.TV_ANISO
+    xf, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 12, flags=fl)
+    xs, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 12, flags=fl | sr3d.SEPARATE_R2C)
+    xg, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 12, flags=fl | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(5))
+    assert torch.equal(xf, xs) and torch.equal(xf, xg)
+    state = torch.zeros(3 * y.size * 8, device="cuda")
+    sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 6, state=state, flags=fl)
+    xr, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 6, state=state, flags=fl | sr3d.RESUME)
+    assert torch.equal(xr, xf)
+    # the state carries the anisotropic dual: |d_a| <= lam/mu per component
+    nu = host(state).reshape((3,) + shape)
+    assert np.abs(nu - O.shrink_aniso(nu, LAM_TV / MU)).max() <= (LAM_TV / MU) * (1 + 1e-5)
+
+
+def test_tv_aniso_batch_matches_single_solves():
+    cases = [((32, 32, 32), (2, 2, 2)), ((16, 6, 64), (2, 2, 2)), ((24, 12, 24), (1, 3, 3))]
+    fl = sr3d.FP64_REDUCE | sr3d.TV_ANISO
+    probs, refs = [], []
+    for i, (shape, rate) in enumerate(cases):
+        p = phantom.make_problem(shape, rate, 1.0, 0.02, 400 + i, n_ellipsoids=6)
+        psf = fit_psf(p["psf"], shape)
+        y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+        probs.append(dict(y=dev(y), psf=dev(psf), rate=rate, lam=LAM_TV, mu=MU, max_iter=9,
+                          tol=0.0))
+        refs.append(O.admm_tv(y, psf, rate, LAM_TV, MU, 9, aniso=True).x)
+    xs, sts = sr3d.batch(probs, flags=fl)
+    for x, st, ref, q in zip(xs, sts, refs, probs):
+        single, _ = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 9, flags=fl)
+        assert st.iters == 9
+        assert O.rel_l2(host(x), host(single)) < 1e-6
+        assert O.rel_l2(host(x), ref) < TOL
+
+
 @pytest.mark.parametrize("unfused", [False, True])
 def test_batch_mixes_fused_and_unfused_volumes(unfused):
     cases = [((8, 32, 32), (2, 2, 2)), ((32, 32, 32), (2, 2, 2)), ((16, 12, 12), (3, 4, 2)),
