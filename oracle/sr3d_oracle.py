@@ -41,6 +41,8 @@ __all__ = [
     "WORKERS", "hr_shape_of", "lr_shape_of", "psf_to_otf", "blur", "blur_adjoint",
     "decimate", "zero_fill", "degrade", "fold", "unfold", "diff_symbol_sq",
     "grad", "grad_adjoint", "shrink", "shrink_aniso", "tikhonov", "tikhonov_objective",
+    "haar3", "haar3_inverse", "haar_detail_mask", "shrink_detail", "wavelet_objective",
+    "admm_wavelet",
     "x_update", "AdmmResult", "admm_tv", "min_norm_dual", "tv_objective", "data_term", "psnr",
     "rel_l2",
 ]
@@ -386,6 +388,124 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
         s_norm = mu * float(np.sqrt(np.sum(grad_adjoint(u_new - u) ** 2)))
         pri_den = max(float(np.sqrt(np.sum(Lx * Lx))), float(np.sqrt(np.sum(u_new * u_new))))
         dual_den = mu * float(np.sqrt(np.sum(grad_adjoint(d_new) ** 2)))
+        prel, drel = _rel(r_norm, pri_den), _rel(s_norm, dual_den)
+        if record:
+            hist.append((prel, drel))
+        if callback is not None:
+            callback(it, x, u, d, u_new, d_new)
+        u, d = u_new, d_new
+        if tol > 0 and prel <= tol and drel <= (tol if not tol_dual else tol_dual):
+            converged = True
+            break
+    return AdmmResult(x=x, u=u, d=d, iters=it, converged=converged,
+                      primal_rel=prel, dual_rel=drel, history=hist)
+
+
+# ---------------------------------------------------------------------------
+# l1 in an orthonormal wavelet basis through the same x-step (Sec. III-B):
+# phi(W x) = sum of |detail coefficients| of the 3D Haar transform W. With
+# W^T W = I the x-step of Algorithm 1 becomes the Tikhonov problem eq. (5)
+# with 2 lam -> mu and xbar = W^T (u - d), solved by eq. (12).
+# ---------------------------------------------------------------------------
+
+_SQRT_HALF = np.sqrt(0.5)
+
+
+def _haar_axis(a, axis):
+    """(a, b) -> ((a + b)/sqrt 2, (a - b)/sqrt 2) on neighbouring pairs along
+    ``axis`` (even index first); its own inverse."""
+    a = np.moveaxis(a, axis, 0)
+    e, o = a[0::2].copy(), a[1::2].copy()
+    a[0::2] = (e + o) * _SQRT_HALF
+    a[1::2] = (e - o) * _SQRT_HALF
+    return np.moveaxis(a, 0, axis)
+
+
+def haar3(x, levels=1):
+    """W x: the orthonormal 3D Haar transform with ``levels`` levels, in place.
+
+    Level l transforms the previous level's approximation coefficients, which
+    sit at the positions that are multiples of 2^(l-1) along every axis: the
+    pair map above along m, n and s in turn. Afterwards the approximation
+    coefficients sit at the multiples of 2^levels and every other position
+    holds a detail coefficient. Every dimension must be a multiple of
+    2^levels.
+    """
+    c = np.array(x, np.float64, copy=True)
+    for lev in range(levels):
+        st = 2 ** lev
+        sub = c[::st, ::st, ::st]
+        for axis in (2, 1, 0):
+            sub = _haar_axis(sub, axis)
+        c[::st, ::st, ::st] = sub
+    return c
+
+
+def haar3_inverse(c, levels=1):
+    """W^T c = W^{-1} c (the transform is orthonormal): the levels in reverse."""
+    x = np.array(c, np.float64, copy=True)
+    for lev in reversed(range(levels)):
+        st = 2 ** lev
+        sub = x[::st, ::st, ::st]
+        for axis in (0, 1, 2):
+            sub = _haar_axis(sub, axis)
+        x[::st, ::st, ::st] = sub
+    return x
+
+
+def haar_detail_mask(shape, levels=1):
+    """True at detail coefficients, False at the approximation ones."""
+    st = 2 ** levels
+    mask = np.ones(shape, bool)
+    mask[::st, ::st, ::st] = False
+    return mask
+
+
+def shrink_detail(nu, thr, mask):
+    """Step 5b for phi = thr-weighted l1 of the details: soft threshold where
+    ``mask``, identity on the approximation coefficients."""
+    return np.where(mask, np.sign(nu) * np.maximum(0.0, np.abs(nu) - thr), nu)
+
+
+def wavelet_objective(x, y, psf, rate, lam, levels=1):
+    """1/2 ||y - D H x||^2 + lam sum |detail coefficients of W x|."""
+    otf = psf_to_otf(psf, x.shape)
+    c = haar3(x, levels)
+    return data_term(x, y, otf, rate) + lam * float(np.sum(np.abs(c[haar_detail_mask(x.shape, levels)])))
+
+
+def admm_wavelet(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, levels=1, record=False,
+                 callback=None, tol_dual=None):
+    """Algorithm 1 with L replaced by the orthonormal Haar transform W.
+
+    Initialisation as admm_tv: nu = W x0, u = prox(nu), d = nu - u.
+    Loop: 5a x = argmin 1/2||y - DHx||^2 + mu/2 ||W x - u + d||^2, i.e.
+    ``tikhonov(y, psf, rate, mu/2, xbar=W^T(u - d))``; 5b nu = W x + d,
+    u' = shrink_detail(nu, lam/mu); 5c d' = d + (W x - u').
+    Stopping rule as admm_tv with L^T -> W^T: ||W^T z|| = ||z||.
+    """
+    y = np.asarray(y, np.float64)
+    hr = hr_shape_of(y.shape, rate)
+    mask = haar_detail_mask(hr, levels)
+    thr = lam / mu
+    x = np.zeros(hr) if x0 is None else np.asarray(x0, np.float64).copy()
+    nu = haar3(x, levels)
+    u = shrink_detail(nu, thr, mask)
+    d = nu - u
+    hist = []
+    it = 0
+    converged = False
+    prel = drel = float("inf")
+    for it in range(1, max_iter + 1):
+        x = tikhonov(y, psf, rate, 0.5 * mu, xbar=haar3_inverse(u - d, levels))
+        c = haar3(x, levels)
+        nu = c + d
+        u_new = shrink_detail(nu, thr, mask)
+        d_new = d + (c - u_new)
+        r_norm = float(np.sqrt(np.sum((c - u_new) ** 2)))
+        s_norm = mu * float(np.sqrt(np.sum((u_new - u) ** 2)))
+        pri_den = max(float(np.sqrt(np.sum(c * c))), float(np.sqrt(np.sum(u_new * u_new))))
+        dual_den = mu * float(np.sqrt(np.sum(d_new * d_new)))
         prel, drel = _rel(r_norm, pri_den), _rel(s_norm, dual_den)
         if record:
             hist.append((prel, drel))
