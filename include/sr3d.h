@@ -109,6 +109,17 @@ typedef struct {
                                   the same x-step serves (Sec. III-B). Step 5b becomes a soft
                                   threshold of every component; the objective reports the l1
                                   form. Every other step is unchanged. */
+#define SR3D_REG_HAAR    0x100000 /* regulariser lambda sum |detail coefficients of W x|, W the
+                                  orthonormal 3D Haar transform with SR3D_HAAR_LEVELS levels
+                                  (approximation coefficients not penalised): l1 in an orthogonal
+                                  wavelet basis, another regulariser the same x-step serves
+                                  (Sec. III-B). With W^T W = I, step 5a is the Tikhonov solve of
+                                  eq. (12) with 2 lambda -> mu and xbar = W^T (u - d); steps 5b/5c
+                                  act on the coefficients (soft threshold of the details). The
+                                  state nu = W x + d is the first N_h floats of problem.state.
+                                  Every HR dimension must be a multiple of 2^levels. Not with
+                                  SR3D_TV_ANISO, SR3D_WARM_DUAL or sr3d_batch. */
+#define SR3D_HAAR_LEVELS(j) (((j) & 0xf) << 16)  /* Haar levels for SR3D_REG_HAAR, 1..8 (0: 1) */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */

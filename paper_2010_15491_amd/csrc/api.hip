@@ -188,7 +188,16 @@ struct TvWs {
   bool fused;  // this solve uses the fused x-update (set by the caller)
   bool fsten;  // ... and the stencil with the m-axis R2C fused in
   bool aniso;  // anisotropic TV (SR3D_TV_ANISO)
+  bool haar;   // l1 of Haar details (SR3D_REG_HAAR): Tikhonov fold + wavelet kernels
+  int levels;  // Haar levels
+  int nbSwav;  // workgroups of the wavelet ADMM kernel
 };
+
+// Haar levels of SR3D_REG_HAAR (bits 16-19 of the flags; 0 means 1).
+int haar_levels(int flags) {
+  const int lv = (flags >> 16) & 0xf;
+  return lv ? lv : 1;
+}
 
 // Workspace of one TV solve. nu[0] is only used when the caller passes no
 // state buffer. The fused x-update buffers exist whenever the geometry has a
@@ -197,8 +206,11 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   Carve c{base, 0};
   L->nbStile = stencil_plan(g.S, g.N, g.M).blocks;
   L->nbSrow = g.sp.fused && stencil_r2c_supported(g.M) ? stencil_r2c_plan(g.S, g.N, g.M).blocks : 0;
+  L->nbSwav = wavelet_blocks(g.S, g.N, g.M);
   L->nbS = L->nbStile;
   L->fsten = false;
+  L->haar = false;
+  L->levels = 1;
   FoldArgs fa{};
   fa.Sl = g.Sl; fa.Nl = g.Nl; fa.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
   L->nbFold = fold_blocks(fa);
@@ -206,7 +218,9 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->nbF = L->nbFold;
   L->fused = false;
   L->ctrl = c.take<Ctrl>(1);
-  L->partS = c.take<double>((size_t)6 * (L->nbStile > L->nbSrow ? L->nbStile : L->nbSrow));
+  int nbs_max = L->nbStile > L->nbSrow ? L->nbStile : L->nbSrow;
+  nbs_max = nbs_max > L->nbSwav ? nbs_max : L->nbSwav;
+  L->partS = c.take<double>((size_t)6 * nbs_max);
   L->partF = c.take<double>((size_t)(L->nbFold > L->nbFused ? L->nbFold : L->nbFused));
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
   L->lam = c.take<float2>(g.nspec);
@@ -236,7 +250,15 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->nbF = L->fused ? L->nbFused : L->nbFold;
   L->fsten = L->fused && L->nbSrow > 0 && !(flags & SR3D_SEPARATE_R2C);
   L->aniso = (flags & SR3D_TV_ANISO) != 0;
+  L->haar = (flags & SR3D_REG_HAAR) != 0;
+  L->levels = haar_levels(flags);
   L->nbS = L->fsten ? L->nbSrow : L->nbStile;
+  if (L->haar) {
+    // the x-step is the Tikhonov fold on the natural spectrum layout
+    L->fused = L->fsten = false;
+    L->nbF = L->nbFold;
+    L->nbS = L->nbSwav;
+  }
 }
 
 SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem *p) {
@@ -318,6 +340,14 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
   if ((flags & SR3D_RESUME) && !p->state) return fail(SR3D_ERR_INVALID_ARG, "SR3D_RESUME needs problem.state");
   if ((flags & SR3D_WARM_DUAL) && p->x0 && p->x0 == p->x)
     return fail(SR3D_ERR_INVALID_ARG, "SR3D_WARM_DUAL needs x0 distinct from x");
+  if (flags & SR3D_REG_HAAR) {
+    const int lv = haar_levels(flags), q = 1 << lv;
+    if (lv > 8) return fail(SR3D_ERR_INVALID_ARG, "SR3D_HAAR_LEVELS must be at most 8");
+    if (g->S % q || g->N % q || g->M % q)
+      return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR needs every HR dimension a multiple of 2^levels");
+    if (flags & (SR3D_TV_ANISO | SR3D_WARM_DUAL))
+      return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR excludes SR3D_TV_ANISO and SR3D_WARM_DUAL");
+  }
   if (p->x == p->y || p->x == p->psf) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
   return SR3D_OK;
 }
@@ -356,6 +386,22 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
     if ((e = hipStreamSynchronize(st))) return e;  // the host images above are locals
   }
   const float thr = p->lambda_tv / p->mu;
+  if (L.haar) {
+    // nu0 = W x0 (d = 0), or the given state; then xbar = W^T (u - d).
+    if (flags & SR3D_RESUME) {
+      if ((e = wavelet_admm(L.theta, nu0, nullptr, g.S, g.N, g.M, L.levels, thr, 2, nullptr, false,
+                            nullptr, st)))
+        return e;
+    } else {
+      if (p->x0) e = haar3(p->x0, L.theta, g.S, g.N, g.M, L.levels, false, nullptr, st);
+      else e = fill_zero(L.theta, (size_t)g.NH, st);
+      if (e) return e;
+      if ((e = wavelet_admm(L.theta, nullptr, nu0, g.S, g.N, g.M, L.levels, thr, 1, nullptr, false,
+                            nullptr, st)))
+        return e;
+    }
+    return haar3(nullptr, L.theta, g.S, g.N, g.M, L.levels, true, nullptr, st);
+  }
   if (flags & SR3D_RESUME) {
     if ((e = theta_from_nu(nu0, L.theta, g.S, g.N, g.M, thr, L.aniso, st))) return e;
     return theta0_spectrum(g, L, st);
@@ -387,8 +433,33 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
 // iteration's first launch (fused path, not the first iteration of an
 // enqueued chunk: `merged`), or in its own launch at the end of a chunk
 // (`last`), so the host sees complete statistics after every chunk.
+// One iteration of the wavelet form: x-step by the Tikhonov fold (A = mu,
+// xbar in theta), then W, steps 5b/5c and W^T back into theta.
+hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
+                             float *const nu[2], int k, bool fp64, hipStream_t st) {
+  const int *done = &L.ctrl->done;
+  hipError_t e;
+  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+  FoldArgs fa = make_fold(g);
+  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+  fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 0;
+  fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+  if ((e = fold_solve(fa, fp64, st))) return e;
+  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  prof_begin(kStStencil, st);
+  e = haar3(p->x, L.theta, g.S, g.N, g.M, L.levels, false, done, st);
+  if (!e)
+    e = wavelet_admm(L.theta, nu[(k - 1) & 1], nu[k & 1], g.S, g.N, g.M, L.levels,
+                     p->lambda_tv / p->mu, 0, L.partS, fp64, done, st);
+  if (!e) e = haar3(nullptr, L.theta, g.S, g.N, g.M, L.levels, true, done, st);
+  prof_end(st);
+  if (e) return e;
+  return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
+}
+
 hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
                         int k, bool fp64, hipStream_t st, bool merged, bool last) {
+  if (L.haar) return wavelet_iteration(g, L, p, nu, k, fp64, st);
   const int *done = &L.ctrl->done;
   hipError_t e;
   // The iteration's first launch can carry the previous reduction: the R2C
@@ -732,6 +803,7 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
 int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
               size_t ws_bytes, hipStream_t st) {
   if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
+  if (flags & SR3D_REG_HAAR) return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR is not supported by sr3d_batch");
   Geometry g0;
   for (int i = 0; i < count; ++i) {
     int rc = check_problem(&p[i], flags, &g0);

@@ -291,6 +291,20 @@ hipError_t diff_tables(float *g, int S, int N, int M, hipStream_t st);  // g = [
 hipError_t ctrl_init(Ctrl *c, int max_iter, float tol, float tol_dual, float mu, float lam,
                      double inv_nl, hipStream_t st);
 hipError_t fill_zero(float *p, size_t n, hipStream_t st);
+
+// l1 of orthonormal 3D Haar details through the same x-step (haar.hip).
+// haar3: `levels` levels of W (or W^T with `inverse`) of an S x N x M volume,
+// every dimension a multiple of 2^levels; the forward transform reads `in`
+// and works in place on `out`, the inverse works in place on `out`.
+hipError_t haar3(const float *in, float *out, int S, int N, int M, int levels, bool inverse,
+                 const int *done, hipStream_t st);
+// Steps 5b/5c on coefficients cz = W x, overwritten by u' - d'. mode 0: from
+// the state nu_in, residual sums into part ([6][wavelet_blocks]); 1: from cz
+// with d_prev = 0 (initialisation); 2: cz = u - d of the state nu_in alone.
+hipError_t wavelet_admm(float *cz, const float *nu_in, float *nu_out, int S, int N, int M,
+                        int levels, float thr, int mode, void *part, bool fp64, const int *done,
+                        hipStream_t st);
+int wavelet_blocks(int S, int N, int M);
 hipError_t add_to(float *y, const float *x, size_t n, hipStream_t st);
 hipError_t spectrum_mul(float2 *W, const float2 *Lam, size_t n, float scale, hipStream_t st);
 hipError_t decimate(const float *x, float *y, int S, int N, int M, int dr, int dc, int ds,

@@ -29,6 +29,12 @@ WARM_DUAL = 0x10
 UNFUSED = 0x20
 SEPARATE_R2C = 0x40
 TV_ANISO = 0x80
+REG_HAAR = 0x100000
+
+
+def HAAR_LEVELS(j):
+    """Haar levels for REG_HAAR (1..8)."""
+    return (j & 0xF) << 16
 
 
 def CHECK_INTERVAL(k):

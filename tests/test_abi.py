@@ -102,3 +102,57 @@ def test_fft_host_errors():
     assert lib.sr3d_rfft3d(sr3d.Dims(40, 8, 8), 1, 2, None) == -4
     assert lib.sr3d_rfft3d(sr3d.Dims(32, 8, 8), None, 2, None) == -1
     assert lib.sr3d_irfft3d(sr3d.Dims(0, 8, 8), 1, 2, None) == -1
+
+
+def _header_flags():
+    text = open(os.path.join(ROOT, "include", "sr3d.h")).read()
+    return {m.group(1): int(m.group(2), 16)
+            for m in re.finditer(r"#define SR3D_([A-Z0-9_]+)\s+(0x[0-9a-fA-F]+)\b", text)}
+
+
+def test_binding_flag_values_match_the_header():
+    flags = _header_flags()
+    for name in ("FP64_REDUCE", "RESUME", "USE_GRAPH", "PROFILE", "WARM_DUAL", "UNFUSED",
+                 "SEPARATE_R2C", "TV_ANISO", "REG_HAAR"):
+        assert getattr(sr3d, name) == flags[name], name
+    # single bits, none inside the CHECK_INTERVAL (8-15) or HAAR_LEVELS (16-19) fields
+    bits = [flags[n] for n in flags if n not in ("ERR_INVALID_ARG",)]
+    for b in bits:
+        assert b & (b - 1) == 0 and b & 0xFFF00 == 0, hex(b)
+    assert sr3d.CHECK_INTERVAL(255) == 0xFF00 and sr3d.HAAR_LEVELS(15) == 0xF0000
+
+
+def test_header_compiles_as_c():
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc")
+    rocm_inc = "/opt/rocm/include"
+    if not cc or not os.path.isdir(rocm_inc):
+        pytest.skip("needs gcc and the ROCm headers")
+    src = ('#include "sr3d.h"\n'
+           "int f(void) { return SR3D_CHECK_INTERVAL(3) | SR3D_HAAR_LEVELS(2) | SR3D_REG_HAAR"
+           " | SR3D_TV_ANISO | SR3D_SEPARATE_R2C; }\n")
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "h.c")
+        with open(c, "w") as f:
+            f.write(src)
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                            "-I", os.path.join(ROOT, "include"), "-I", rocm_inc, "-c", c, "-o",
+                            os.path.join(td, "h.o")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_wavelet_host_argument_errors():
+    lib = sr3d.load()
+    lv2 = sr3d.REG_HAAR | sr3d.HAAR_LEVELS(2)
+    p = _prob(hr=(32, 32, 6), rate=(2, 2, 2))  # m = 6 is no multiple of 4
+    assert sr3d.STATUS[lib.sr3d_tv_admm(ctypes.byref(p), lv2, None, None, 0, None)] == \
+        "SR3D_ERR_INVALID_ARG"
+    p = _prob()
+    assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.REG_HAAR | sr3d.TV_ANISO, None, None, 0,
+                            None) == -1
+    assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.REG_HAAR | sr3d.HAAR_LEVELS(9), None, None, 0,
+                            None) == -1
+    arr = (sr3d.Problem * 1)(_prob())
+    assert lib.sr3d_batch(arr, 1, sr3d.REG_HAAR, None, None, 0, None) == -1

@@ -505,6 +505,51 @@ def test_tv_aniso_batch_matches_single_solves():
         assert O.rel_l2(host(x), ref) < TOL
 
 
+# l1 of orthonormal 3D Haar details through the same x-step (Tikhonov fold).
+WAVELET_CASES = [
+    ((16, 16, 16), (1, 1, 1), 1),
+    ((32, 32, 32), (2, 2, 2), 1),
+    ((32, 16, 32), (2, 1, 2), 2),
+    ((16, 16, 32), (1, 1, 1), 3),
+    ((24, 24, 48), (2, 2, 2), 3),
+]
+
+
+@pytest.mark.parametrize("shape,rate,levels", WAVELET_CASES)
+def test_wavelet_l1_matches_oracle(shape, rate, levels):
+    y, psf, _ = problem(shape, rate, 1.0, 0.02, 51, n_ell=6)
+    ref = O.admm_wavelet(y, psf, rate, LAM_TV, MU, 10, levels=levels)
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10,
+                         flags=sr3d.FP64_REDUCE | sr3d.REG_HAAR | sr3d.HAAR_LEVELS(levels))
+    err = O.rel_l2(host(x), ref.x)
+    print(f"{shape} {rate} levels {levels}: rel-L2 {err:.2e}")
+    assert err < TOL
+    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
+    assert np.isclose(st.objective, O.wavelet_objective(host(x), y, psf, rate, LAM_TV, levels),
+                      rtol=1e-4)
+
+
+def test_wavelet_l1_resume_graph_and_tolerance_stop():
+    shape, rate, levels = (16, 16, 32), (1, 1, 1), 2
+    y, psf, _ = problem(shape, rate, 1.0, 0.02, 52, n_ell=6)
+    Y, P = dev(y), dev(psf)
+    fl = sr3d.FP64_REDUCE | sr3d.REG_HAAR | sr3d.HAAR_LEVELS(levels)
+    x12, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 12, flags=fl)
+    xg, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 12, flags=fl | sr3d.USE_GRAPH | sr3d.CHECK_INTERVAL(5))
+    assert torch.equal(x12, xg)
+    state = torch.zeros(3 * y.size, device="cuda")
+    sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 7, state=state, flags=fl)
+    xr, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, state=state, flags=fl | sr3d.RESUME)
+    assert torch.equal(xr, x12)
+    tol = 1e-3
+    ref = O.admm_wavelet(y, psf, rate, LAM_TV, MU, 300, tol=tol, levels=levels)
+    x, st = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 300, tol=tol, flags=fl | sr3d.CHECK_INTERVAL(1))
+    assert ref.converged and st.converged and abs(st.iters - ref.iters) <= 1
+    assert O.rel_l2(host(x), O.admm_wavelet(y, psf, rate, LAM_TV, MU, st.iters,
+                                            levels=levels).x) < TOL
+
+
 @pytest.mark.parametrize("unfused", [False, True])
 def test_batch_mixes_fused_and_unfused_volumes(unfused):
     cases = [((8, 32, 32), (2, 2, 2)), ((32, 32, 32), (2, 2, 2)), ((16, 12, 12), (3, 4, 2)),
