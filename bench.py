@@ -62,6 +62,9 @@ def alg_bytes_per_voxel(stage, hr, rate):
         "admm_stencil": 4.0 + 12.0 + 12.0 + 4.0,
         # the same with the m-axis R2C fused in: Theta's half spectrum written
         "stencil_r2c": 4.0 + 12.0 + 12.0 + spec,
+        # Haar form, steps 5b/5c and W, W^T: x and nu_old read, nu_new and
+        # xbar written (one plane each)
+        "wavelet": 4.0 + 4.0 + 4.0 + 4.0,
     }
     return table.get(stage)
 
@@ -137,6 +140,9 @@ def main():
                          "(SR3D_SEPARATE_R2C) instead of the fused stencil")
     ap.add_argument("--aniso", action="store_true",
                     help="tv256: anisotropic TV (SR3D_TV_ANISO) instead of the isotropic default")
+    ap.add_argument("--haar", type=int, default=0, metavar="LEVELS",
+                    help="tv256: l1 of orthonormal Haar details with LEVELS levels "
+                         "(SR3D_REG_HAAR) instead of TV")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a dispatch "
                          "of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -168,7 +174,8 @@ def main():
                       x=x)
     ws = torch.empty(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [p]), dtype=torch.uint8, device=dev)
     base_flags = (sr3d.FP64_REDUCE | (sr3d.SEPARATE_R2C if args.separate_r2c else 0)
-                  | (sr3d.TV_ANISO if args.aniso else 0))
+                  | (sr3d.TV_ANISO if args.aniso else 0)
+                  | (sr3d.REG_HAAR | sr3d.HAAR_LEVELS(args.haar) if args.haar else 0))
     flags = base_flags | (0 if args.no_profile else sr3d.PROFILE)
     flags_all = flags
     # FFT tile variants: timed once on this device, outside the timed steps.
@@ -252,7 +259,8 @@ def main():
                    "converged": stats.converged, "primal_rel": stats.primal_rel,
                    "dual_rel": stats.dual_rel, "reductions": "fp64",
                    "stencil": "tiled + separate R2C" if args.separate_r2c else "fused R2C",
-                   "regulariser": "anisotropic TV" if args.aniso else "isotropic TV",
+                   "regulariser": (f"l1 of {args.haar}-level Haar details" if args.haar
+                                   else "anisotropic TV" if args.aniso else "isotropic TV"),
                    "fft_tiles_kind_len_variant": fft_tiles,
                    "parallelism": "single_gpu"},
         "roofline": roofline,

@@ -32,7 +32,7 @@ long g_prof_n[kStCount] = {0};
 unsigned g_prof_mask = ~0u;  // stages timed under SR3D_PROFILE
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
                                      "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
-                                     "reduce_test", "solve_s", "stencil_r2c", "setup"};
+                                     "reduce_test", "solve_s", "stencil_r2c", "wavelet", "setup"};
 }  // namespace
 
 void prof_begin(int stage, hipStream_t st) {
@@ -446,7 +446,7 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
   fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
   if ((e = fold_solve(fa, fp64, st))) return e;
   if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
-  prof_begin(kStStencil, st);
+  prof_begin(kStWavelet, st);
   e = haar3(p->x, L.theta, g.S, g.N, g.M, L.levels, false, done, st);
   if (!e)
     e = wavelet_admm(L.theta, nu[(k - 1) & 1], nu[k & 1], g.S, g.N, g.M, L.levels,

@@ -52,7 +52,7 @@ struct FastDiv {
 // launch on its stream when the calling thread has profiling switched on.
 enum Stage {
   kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
-  kStStencil, kStReduce, kStSolveS, kStStencilR2c, kStSetup, kStCount
+  kStStencil, kStReduce, kStSolveS, kStStencilR2c, kStWavelet, kStSetup, kStCount
 };
 void prof_begin(int stage, hipStream_t st);
 void prof_end(hipStream_t st);
