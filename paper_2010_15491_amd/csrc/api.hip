@@ -207,6 +207,8 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->nbStile = stencil_plan(g.S, g.N, g.M).blocks;
   L->nbSrow = g.sp.fused && stencil_r2c_supported(g.M) ? stencil_r2c_plan(g.S, g.N, g.M).blocks : 0;
   L->nbSwav = wavelet_blocks(g.S, g.N, g.M);
+  // the one-pass wavelet kernel has the most workgroups at one level
+  const int nb_wf = wavelet_fused_blocks(g.S, g.N, g.M, 1);
   L->nbS = L->nbStile;
   L->fsten = false;
   L->haar = false;
@@ -220,6 +222,7 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->ctrl = c.take<Ctrl>(1);
   int nbs_max = L->nbStile > L->nbSrow ? L->nbStile : L->nbSrow;
   nbs_max = nbs_max > L->nbSwav ? nbs_max : L->nbSwav;
+  nbs_max = nbs_max > nb_wf ? nbs_max : nb_wf;
   L->partS = c.take<double>((size_t)6 * nbs_max);
   L->partF = c.take<double>((size_t)(L->nbFold > L->nbFused ? L->nbFold : L->nbFused));
   L->g = c.take<float>((size_t)g.M + g.N + g.S);
@@ -257,7 +260,7 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
     // the x-step is the Tikhonov fold on the natural spectrum layout
     L->fused = L->fsten = false;
     L->nbF = L->nbFold;
-    L->nbS = L->nbSwav;
+    L->nbS = L->levels <= 3 ? wavelet_fused_blocks(g.S, g.N, g.M, L->levels) : L->nbSwav;
   }
 }
 
@@ -388,6 +391,11 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   const float thr = p->lambda_tv / p->mu;
   if (L.haar) {
     // nu0 = W x0 (d = 0), or the given state; then xbar = W^T (u - d).
+    if (L.levels <= 3) {
+      const bool resume = (flags & SR3D_RESUME) != 0;
+      return wavelet_fused(p->x0, resume ? nu0 : nullptr, resume ? nullptr : nu0, L.theta, g.S,
+                           g.N, g.M, L.levels, thr, resume ? 2 : 1, nullptr, false, nullptr, st);
+    }
     if (flags & SR3D_RESUME) {
       if ((e = wavelet_admm(L.theta, nu0, nullptr, g.S, g.N, g.M, L.levels, thr, 2, nullptr, false,
                             nullptr, st)))
@@ -447,11 +455,17 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
   if ((e = fold_solve(fa, fp64, st))) return e;
   if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
   prof_begin(kStWavelet, st);
-  e = haar3(p->x, L.theta, g.S, g.N, g.M, L.levels, false, done, st);
-  if (!e)
-    e = wavelet_admm(L.theta, nu[(k - 1) & 1], nu[k & 1], g.S, g.N, g.M, L.levels,
-                     p->lambda_tv / p->mu, 0, L.partS, fp64, done, st);
-  if (!e) e = haar3(nullptr, L.theta, g.S, g.N, g.M, L.levels, true, done, st);
+  const float thr = p->lambda_tv / p->mu;
+  if (L.levels <= 3) {
+    e = wavelet_fused(p->x, nu[(k - 1) & 1], nu[k & 1], L.theta, g.S, g.N, g.M, L.levels, thr, 0,
+                      L.partS, fp64, done, st);
+  } else {
+    e = haar3(p->x, L.theta, g.S, g.N, g.M, L.levels, false, done, st);
+    if (!e)
+      e = wavelet_admm(L.theta, nu[(k - 1) & 1], nu[k & 1], g.S, g.N, g.M, L.levels, thr, 0,
+                       L.partS, fp64, done, st);
+    if (!e) e = haar3(nullptr, L.theta, g.S, g.N, g.M, L.levels, true, done, st);
+  }
   prof_end(st);
   if (e) return e;
   return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);

@@ -129,6 +129,176 @@ __global__ __launch_bounds__(kThreads) void k_wavelet_admm(float *cz, const floa
   }
 }
 
+// All of steps 5b/5c with W and W^T for J <= 3 levels in one pass: a
+// workgroup takes tiles of 2^J (s) x 2^J (n) x up to 64 (m) voxels (whole
+// 2^J-cubes, which W maps onto themselves), transforms x in LDS, applies the
+// shrink and dual update with nu read and written in row order, transforms
+// back and stores xbar. Modes as k_wavelet_admm: 0 iteration, 1 start from x
+// (x null: zero), 2 resume from nu_in.
+constexpr int kWavTM = 64;
+
+template <int J>
+__device__ __forceinline__ void tile_levels(float *t, int tmv, bool inverse) {
+  constexpr int T = 1 << J;
+  for (int k = 0; k < J; ++k) {
+    const int lev = inverse ? J - 1 - k : k;
+    const int st = 1 << lev;
+    const int bs = T / (2 * st), bm = tmv / (2 * st);
+    const int nblk = bs * bs * bm;
+    for (int q = threadIdx.x; q < nblk; q += kThreads) {
+      const int ic = q % bm, r = q / bm, ib = r % bs, ia = r / bs;
+      const int base = ((2 * ia * st) * T + 2 * ib * st) * kWavTM + 2 * ic * st;
+      float v[8];
+      int o[8];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int qq = (a * 2 + b2) * 2 + c;
+            o[qq] = base + (a * st * T + b2 * st) * kWavTM + c * st;
+            v[qq] = t[o[qq]];
+          }
+      if (inverse) {
+        haar_pairs(v, 4);
+        haar_pairs(v, 2);
+        haar_pairs(v, 1);
+      } else {
+        haar_pairs(v, 1);
+        haar_pairs(v, 2);
+        haar_pairs(v, 4);
+      }
+#pragma unroll
+      for (int qq = 0; qq < 8; ++qq) t[o[qq]] = v[qq];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename Acc, int J, int MODE>
+__global__ __launch_bounds__(kThreads) void k_wavelet_fused(const float *__restrict__ x,
+                                                            const float *__restrict__ nu_in,
+                                                            float *__restrict__ nu_out,
+                                                            float *__restrict__ xbar, int S, int N,
+                                                            int M, float thr, void *part,
+                                                            const int *done) {
+  constexpr int T = 1 << J, TE = T * T * kWavTM;
+  if (done && *done) return;
+  __shared__ float t[TE];
+  __shared__ Acc sh[6 * (kThreads / 64)];
+  const int tm = (M + kWavTM - 1) / kWavTM, tn = N / T, ts = S / T;
+  const long ntiles = (long)ts * tn * tm;
+  const long plane = (long)N * M;
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int im = (int)(tile % tm);
+    const long r = tile / tm;
+    const int in_ = (int)(r % tn), is = (int)(r / tn);
+    const int m0 = im * kWavTM, tmv = min(kWavTM, M - m0);
+    const long g0 = (long)is * T * plane + (long)in_ * T * M + m0;
+    // element e of the tile: row e / kWavTM = a T + b (s offset a, n offset b), m offset e % kWavTM
+    auto gidx = [&](int e) {
+      const int row = e / kWavTM, m = e % kWavTM;
+      return g0 + (long)(row / T) * plane + (long)(row % T) * M + m;
+    };
+    if (MODE != 2) {
+      for (int e = threadIdx.x; e < TE; e += kThreads)
+        if (e % kWavTM < tmv) t[e] = x ? x[gidx(e)] : 0.f;
+      __syncthreads();
+      tile_levels<J>(t, tmv, false);
+    }
+    for (int e = threadIdx.x; e < TE; e += kThreads) {
+      const int m = e % kWavTM;
+      if (m >= tmv) continue;
+      const int row = e / kWavTM;
+      // approximation coefficients: multiples of 2^J along every axis, i.e.
+      // the tile's first row and every 2^J-th m
+      const bool detail = row != 0 || (m % T) != 0;
+      const float th = detail ? thr : 0.f;
+      const long gi = gidx(e);
+      if (MODE == 2) {
+        const float nu = nu_in[gi];
+        const float u = soft(nu, th);
+        t[e] = u - (nu - u);
+        continue;
+      }
+      const float c = t[e];
+      float dprev = 0.f, uold = 0.f;
+      if (MODE == 0) {
+        const float nuo = nu_in[gi];
+        uold = soft(nuo, th);
+        dprev = nuo - uold;
+      }
+      const float nu = c + dprev;
+      const float u = soft(nu, th);
+      const float d = nu - u;
+      nu_out[gi] = nu;
+      t[e] = u - d;
+      if (MODE == 0) {
+        const float rp = c - u, du = u - uold;
+        acc[0] += rp * rp;
+        acc[1] += c * c;
+        acc[2] += u * u;
+        acc[3] += detail ? fabsf(c) : 0.f;
+        acc[4] += du * du;
+        acc[5] += d * d;
+      }
+    }
+    __syncthreads();
+    tile_levels<J>(t, tmv, true);
+    for (int e = threadIdx.x; e < TE; e += kThreads)
+      if (e % kWavTM < tmv) xbar[gidx(e)] = t[e];
+    __syncthreads();  // the tile buffer is reloaded for the next tile
+  }
+  if (MODE != 0) return;
+  Acc acc_t[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) acc_t[q] = (Acc)acc[q];
+  block_reduce_n<Acc>(acc_t, 6, sh);
+  if (threadIdx.x == 0) {
+    Acc *p = reinterpret_cast<Acc *>(part);
+    for (int q = 0; q < 6; ++q) p[(long)q * gridDim.x + blockIdx.x] = acc_t[q];
+  }
+}
+
+int wavelet_fused_blocks(int S, int N, int M, int levels) {
+  const int T = 1 << levels;
+  const long tiles = (long)(S / T) * (N / T) * ((M + kWavTM - 1) / kWavTM);
+  return (int)(tiles < 2048 ? (tiles < 1 ? 1 : tiles) : 2048);
+}
+
+template <int J>
+static void launch_wf(const float *x, const float *nu_in, float *nu_out, float *xbar, int S, int N,
+                      int M, float thr, int mode, void *part, bool fp64, const int *done,
+                      hipStream_t st) {
+  const dim3 g((unsigned)wavelet_fused_blocks(S, N, M, J)), b(kThreads);
+  if (mode == 1)
+    hipLaunchKernelGGL((k_wavelet_fused<float, J, 1>), g, b, 0, st, x, nu_in, nu_out, xbar, S, N,
+                       M, thr, part, done);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_wavelet_fused<float, J, 2>), g, b, 0, st, x, nu_in, nu_out, xbar, S, N,
+                       M, thr, part, done);
+  else if (fp64)
+    hipLaunchKernelGGL((k_wavelet_fused<double, J, 0>), g, b, 0, st, x, nu_in, nu_out, xbar, S, N,
+                       M, thr, part, done);
+  else
+    hipLaunchKernelGGL((k_wavelet_fused<float, J, 0>), g, b, 0, st, x, nu_in, nu_out, xbar, S, N,
+                       M, thr, part, done);
+}
+
+hipError_t wavelet_fused(const float *x, const float *nu_in, float *nu_out, float *xbar, int S,
+                         int N, int M, int levels, float thr, int mode, void *part, bool fp64,
+                         const int *done, hipStream_t st) {
+  switch (levels) {
+    case 1: launch_wf<1>(x, nu_in, nu_out, xbar, S, N, M, thr, mode, part, fp64, done, st); break;
+    case 2: launch_wf<2>(x, nu_in, nu_out, xbar, S, N, M, thr, mode, part, fp64, done, st); break;
+    case 3: launch_wf<3>(x, nu_in, nu_out, xbar, S, N, M, thr, mode, part, fp64, done, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 int wavelet_blocks(int S, int N, int M) {
   const long NT = (long)S * N * M;
   long b = (NT + 8L * kThreads - 1) / (8L * kThreads);  // 8 voxels per thread

@@ -305,6 +305,14 @@ hipError_t wavelet_admm(float *cz, const float *nu_in, float *nu_out, int S, int
                         int levels, float thr, int mode, void *part, bool fp64, const int *done,
                         hipStream_t st);
 int wavelet_blocks(int S, int N, int M);
+// W, steps 5b/5c and W^T in one pass for levels <= 3 (modes as wavelet_admm):
+// reads x (mode 0, 1; null in mode 1 means x = 0) and nu_in (mode 0, 2),
+// writes nu_out (mode 0, 1) and xbar; residual sums into part
+// ([6][wavelet_fused_blocks]) in mode 0.
+hipError_t wavelet_fused(const float *x, const float *nu_in, float *nu_out, float *xbar, int S,
+                         int N, int M, int levels, float thr, int mode, void *part, bool fp64,
+                         const int *done, hipStream_t st);
+int wavelet_fused_blocks(int S, int N, int M, int levels);
 hipError_t add_to(float *y, const float *x, size_t n, hipStream_t st);
 hipError_t spectrum_mul(float2 *W, const float2 *Lam, size_t n, float scale, hipStream_t st);
 hipError_t decimate(const float *x, float *y, int S, int N, int M, int dr, int dc, int ds,

@@ -512,6 +512,8 @@ WAVELET_CASES = [
     ((32, 16, 32), (2, 1, 2), 2),
     ((16, 16, 32), (1, 1, 1), 3),
     ((24, 24, 48), (2, 2, 2), 3),
+    ((16, 16, 96), (2, 2, 2), 2),
+    ((16, 32, 32), (1, 1, 1), 4),
 ]
 
 
