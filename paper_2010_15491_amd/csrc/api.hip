@@ -257,9 +257,10 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->levels = haar_levels(flags);
   L->nbS = L->fsten ? L->nbSrow : L->nbStile;
   if (L->haar) {
-    // the x-step is the Tikhonov fold on the natural spectrum layout
-    L->fused = L->fsten = false;
-    L->nbF = L->nbFold;
+    // The x-step is the Tikhonov solve (A = mu): the fused x-update with
+    // tables gm = 1, gn = gs = 0 where the plan applies, else the fold on the
+    // natural spectrum. The stencil is replaced by the wavelet kernels.
+    L->fsten = false;
     L->nbS = L->levels <= 3 ? wavelet_fused_blocks(g.S, g.N, g.M, L->levels) : L->nbSwav;
   }
 }
@@ -276,6 +277,7 @@ SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem 
   a.mu = p->mu;
   a.scale = (float)(1.0 / (double)g.NH);
   a.partial = L.partF; a.ctrl = L.ctrl; a.done = &L.ctrl->done;
+  a.a_pos = L.haar ? 1 : 0;
   return a;
 }
 
@@ -386,6 +388,15 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
       return e;
     if ((e = hipMemcpyAsync(L.sdesc, &sa, sizeof sa, hipMemcpyHostToDevice, st))) return e;
     if ((e = solve_s_gather(sa, L.lam, L.yh, g.Mlh, st))) return e;
+    std::vector<float> gtab;
+    if (L.haar) {
+      // A = mu * (gm + gn + gs) = mu at every member
+      gtab.assign((size_t)g.M + g.N + g.S, 0.f);
+      for (int i = 0; i < g.M; ++i) gtab[i] = 1.f;
+      if ((e = hipMemcpyAsync(L.g, gtab.data(), sizeof(float) * gtab.size(), hipMemcpyHostToDevice,
+                              st)))
+        return e;
+    }
     if ((e = hipStreamSynchronize(st))) return e;  // the host images above are locals
   }
   const float thr = p->lambda_tv / p->mu;
@@ -447,13 +458,25 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
                              float *const nu[2], int k, bool fp64, hipStream_t st) {
   const int *done = &L.ctrl->done;
   hipError_t e;
-  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
-  FoldArgs fa = make_fold(g);
-  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
-  fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 0;
-  fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
-  if ((e = fold_solve(fa, fp64, st))) return e;
-  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  if (L.fused) {
+    const int *kofp = L.tab, *posk = L.tab + g.Mh;
+    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st)))
+      return e;
+    prof_begin(kStSolveS, st);
+    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
+    prof_end(st);
+    if (e) return e;
+    if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
+      return e;
+  } else {
+    if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+    FoldArgs fa = make_fold(g);
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 0;
+    fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+    if ((e = fold_solve(fa, fp64, st))) return e;
+    if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  }
   prof_begin(kStWavelet, st);
   const float thr = p->lambda_tv / p->mu;
   if (L.levels <= 3) {

@@ -283,7 +283,7 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
       lds[mi[q] >= 0 ? mi[q] : S * T] = xs;
     };
     float2 mean;  // (1/d) sum_b L_b X_b of the new x, for the data residual
-    if (g.js == 0 && g.jn == 0 && g.jm == 0) {
+    if (!a.a_pos && g.js == 0 && g.jn == 0 && g.jm == 0) {
       // Zero-frequency group: member 0 is k = 0 with A = 0. Exact elimination
       // of (1/d) conj(L) L^T X + diag(A) X = B, in FP64.
       const double l0r = lcur[0].x, l0i = lcur[0].y;

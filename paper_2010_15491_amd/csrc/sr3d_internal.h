@@ -207,6 +207,9 @@ struct SolveSArgs {
   void *partial;      // data-term partial sums, one per unit (Acc)
   Ctrl *ctrl;
   const int *done;
+  int a_pos;          // A > 0 at every member (A = mu with gm = 1, gn = gs = 0: the Tikhonov
+                      // x-step of the wavelet form); else A(0) = 0 and the zero-frequency
+                      // group is eliminated exactly
 };
 // Unit structure. The LR columns (j_n, j_m) are split into n-groups (one
 // class {j_n, -j_n}, or the two self-conjugate classes {0} and {N_l/2}) and

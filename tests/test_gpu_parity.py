@@ -517,14 +517,18 @@ WAVELET_CASES = [
 ]
 
 
+@pytest.mark.parametrize("unfused", [False, True])
 @pytest.mark.parametrize("shape,rate,levels", WAVELET_CASES)
-def test_wavelet_l1_matches_oracle(shape, rate, levels):
+def test_wavelet_l1_matches_oracle(shape, rate, levels, unfused):
+    """The Tikhonov x-step through the fused x-update kernel (A = mu at every
+    member) and through the unfused fold."""
     y, psf, _ = problem(shape, rate, 1.0, 0.02, 51, n_ell=6)
     ref = O.admm_wavelet(y, psf, rate, LAM_TV, MU, 10, levels=levels)
     x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10,
-                         flags=sr3d.FP64_REDUCE | sr3d.REG_HAAR | sr3d.HAAR_LEVELS(levels))
+                         flags=sr3d.FP64_REDUCE | sr3d.REG_HAAR | sr3d.HAAR_LEVELS(levels)
+                         | (sr3d.UNFUSED if unfused else 0))
     err = O.rel_l2(host(x), ref.x)
-    print(f"{shape} {rate} levels {levels}: rel-L2 {err:.2e}")
+    print(f"{shape} {rate} levels {levels} unfused {unfused}: rel-L2 {err:.2e}")
     assert err < TOL
     assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
     assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
