@@ -548,6 +548,11 @@ def test_wavelet_l1_resume_graph_and_tolerance_stop():
     sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 7, state=state, flags=fl)
     xr, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, state=state, flags=fl | sr3d.RESUME)
     assert torch.equal(xr, x12)
+    # warm start: nu0 = W x0
+    x0 = f32(O.tikhonov(y, psf, rate, 1e-3))
+    xw, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 6, x0=dev(x0), flags=fl)
+    assert O.rel_l2(host(xw), O.admm_wavelet(y, psf, rate, LAM_TV, MU, 6, x0=x0,
+                                             levels=levels).x) < TOL
     tol = 1e-3
     ref = O.admm_wavelet(y, psf, rate, LAM_TV, MU, 300, tol=tol, levels=levels)
     x, st = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 300, tol=tol, flags=fl | sr3d.CHECK_INTERVAL(1))
