@@ -80,7 +80,8 @@ typedef struct {
 } sr3d_problem;
 
 /* sr3d_problem.state: the ADMM state (u, d) is kept as nu = L x + d_prev
- * (three planes [3][s][n][m], components along m, n, s), from which
+ * (three planes [3][s][n][m], components along m, n, s; with SR3D_REG_HAAR
+ * one plane nu = W x + d_prev in the first N_h floats), from which
  * u = shrink(nu) and d = nu - u (Algorithm 1 steps 5b, 5c). If `state` is
  * non-NULL the solver keeps nu there instead of in the workspace, so the
  * final (u, d) can be read back; with SR3D_RESUME it also supplies the
@@ -149,7 +150,9 @@ int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf
  * group, where Gamma = 1/G is unbounded, by exact elimination), then 5b, 5c.
  * Stops when ||Lx-u'|| <= tol max(||Lx||,||u'||) and
  * mu||L^T(u'-u)|| <= tol_dual mu||L^T d'|| (tol_dual = tol unless set), or
- * after max_iter iterations.
+ * after max_iter iterations. The flags SR3D_TV_ANISO and SR3D_REG_HAAR
+ * select the other regularisers the same x-step serves; with SR3D_REG_HAAR,
+ * L is the Haar transform W in everything above.
  * `stats` (host) may be NULL. */
 int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats,
                  void *ws, size_t ws_bytes, hipStream_t stream);

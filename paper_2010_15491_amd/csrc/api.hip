@@ -1,6 +1,8 @@
 // C ABI of libsr3d: argument checks, workspace layout and the host sequence
 // of kernel launches for the Tikhonov closed form (eq. (12)) and TV-ADMM
-// (Algorithm 1).
+// (Algorithm 1), with isotropic or anisotropic TV or the l1 norm of Haar
+// detail coefficients as the regulariser (the last through the Tikhonov
+// x-step).
 #include <math.h>
 #include <string.h>
 
