@@ -248,8 +248,6 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   return c.off + 256;
 }
 
-// The batch launches the tiled stencil for every volume (one launch for the
-// batch), so it passes SR3D_SEPARATE_R2C.
 void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->fused = g.sp.fused && !(flags & SR3D_UNFUSED);
   L->nbF = L->fused ? L->nbFused : L->nbFold;
@@ -640,7 +638,8 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
 
 struct BatchPlan {
   struct Group {
-    int kind;     // 0..5 FFT kinds, 6 fold, 7 stencil
+    int kind;     // 0..5 FFT kinds, 6 fold, 7 stencil, 8 fused x-update,
+                  // 9 stencil with the m-axis R2C fused in
     int key;      // FFT length / decimation factor
     int variant;  // FFT tile variant
     std::vector<int2> items;
@@ -683,7 +682,8 @@ size_t batch_header(int count, size_t nitems, char *base, BatchHeader *H) {
 // Items of every (stage, class) group for volumes with geometries g; fused[v]
 // selects the fused x-update (kind 8, key S, variant = member bound) for
 // volume v instead of the s-FFTs and the fold.
-size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fused, BatchPlan *plan) {
+size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fused,
+                   const std::vector<char> &fsten, BatchPlan *plan) {
   plan->groups.clear();
   auto group = [&](int kind, int key, int variant) -> BatchPlan::Group & {
     for (auto &x : plan->groups)
@@ -700,6 +700,7 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
       if (kind == kFftR2cM || kind == kFftC2rM) {
         len = G.M;
         if (len == 1) continue;  // copy kernels, launched per volume
+        if (kind == kFftR2cM && fsten[v]) continue;  // done by the fused stencil
         tiles = row_tiles(len, fft_variant(kind, len), (long)G.S * G.N);
       } else if (kind == kFftFwdN || kind == kFftInvN) {
         len = G.N;
@@ -726,9 +727,13 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
     const int nb = fold_blocks(fa);
     for (int t = 0; t < nb; ++t) gr.items.push_back(make_int2(v, t));
   }
-  {
-    auto &gr = group(7, 0, 0);
-    for (int v = 0; v < n; ++v) {
+  for (int v = 0; v < n; ++v) {
+    if (fsten[v]) {
+      auto &gr = group(9, g[v].M, 0);
+      const int nb = stencil_r2c_plan(g[v].S, g[v].N, g[v].M).blocks;
+      for (int t = 0; t < nb; ++t) gr.items.push_back(make_int2(v, t));
+    } else {
+      auto &gr = group(7, 0, 0);
       const int nb = stencil_plan(g[v].S, g[v].N, g[v].M).blocks;
       for (int t = 0; t < nb; ++t) gr.items.push_back(make_int2(v, t));
     }
@@ -742,17 +747,27 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
 // workspace per volume. The header holds the larger of the fused and the
 // unfused item lists, so the size does not depend on the flags; `plan`
 // receives the items for `unfused`.
-size_t batch_workspace(const sr3d_problem *p, int count, bool unfused, std::vector<Geometry> *gs,
+// The header is sized for the largest item list any flags can choose
+// (unfused; fused with the separate stencil and R2C; fused with the fused
+// stencil), so the workspace size does not depend on the flags; `plan` is the
+// one `flags` choose.
+size_t batch_workspace(const sr3d_problem *p, int count, int flags, std::vector<Geometry> *gs,
                        std::vector<size_t> *offs, BatchPlan *plan, size_t *header) {
   gs->resize(count);
   for (int i = 0; i < count; ++i)
     if (check_geometry(p[i].hr, p[i].rate, &p[i].psf_dims, &(*gs)[i])) return 0;
-  std::vector<char> fz(count), none(count, 0);
-  for (int i = 0; i < count; ++i) fz[i] = (*gs)[i].sp.fused ? 1 : 0;
+  std::vector<char> fz(count), fs(count), none(count, 0);
+  for (int i = 0; i < count; ++i) {
+    fz[i] = (*gs)[i].sp.fused ? 1 : 0;
+    fs[i] = fz[i] && stencil_r2c_supported((*gs)[i].M) ? 1 : 0;
+  }
+  const bool unfused = (flags & SR3D_UNFUSED) != 0, separate = (flags & SR3D_SEPARATE_R2C) != 0;
   BatchPlan other;
-  const size_t n_unf = batch_items(*gs, none, unfused ? plan : &other);
-  const size_t n_fus = batch_items(*gs, fz, unfused ? &other : plan);
-  const size_t nitems = n_unf > n_fus ? n_unf : n_fus;
+  const size_t n_unf = batch_items(*gs, none, none, unfused ? plan : &other);
+  const size_t n_sep = batch_items(*gs, fz, none, !unfused && separate ? plan : &other);
+  const size_t n_fst = batch_items(*gs, fz, fs, !unfused && !separate ? plan : &other);
+  size_t nitems = n_unf > n_sep ? n_unf : n_sep;
+  nitems = nitems > n_fst ? nitems : n_fst;
   BatchHeader H;
   *header = batch_header(count, nitems, nullptr, &H);
   size_t off = (*header + 255) & ~(size_t)255;
@@ -833,6 +848,14 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
     prof_end(st);
     if (e) return e;
   }
+  for (auto &gr : plan.groups) {
+    if (gr.kind != 9) continue;
+    prof_begin(kStStencilR2c, st);
+    e = admm_stencil_r2c_batch(gr.key, H.sten, items_of(gr), (int)gr.items.size(), k, fp64,
+                               Ls[0].aniso, st);
+    prof_end(st);
+    if (e) return e;
+  }
   prof_begin(kStReduce, st);
   e = reduce_and_test_batch(H.red, n, H.active, fp64, st);
   prof_end(st);
@@ -852,7 +875,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   std::vector<size_t> offs;
   BatchPlan plan;
   size_t hdr = 0;
-  const size_t need = batch_workspace(p, count, (flags & SR3D_UNFUSED) != 0, &g, &offs, &plan, &hdr);
+  const size_t need = batch_workspace(p, count, flags, &g, &offs, &plan, &hdr);
   if (!need) return fail(SR3D_ERR_INVALID_ARG, "invalid geometry");
   if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
   char *base = reinterpret_cast<char *>(ws);
@@ -863,7 +886,7 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   std::vector<TvWs> Ls(count);
   for (int i = 0; i < count; ++i) {
     tv_layout(g[i], base + offs[i], &Ls[i]);
-    tv_choose_path(g[i], flags | SR3D_SEPARATE_R2C, &Ls[i]);
+    tv_choose_path(g[i], flags, &Ls[i]);
   }
   Ctrl *hc = host_ctrl();
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
@@ -907,7 +930,10 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     sd.a.part = L.partS; sd.a.done = done; sd.a.aniso = L.aniso ? 1 : 0;
     sd.nu[0] = nu0[v];
     sd.nu[1] = L.nu[1];
-    sd.pl = stencil_plan(G.S, G.N, G.M);
+    sd.pl = L.fsten ? stencil_r2c_plan(G.S, G.N, G.M) : stencil_plan(G.S, G.N, G.M);
+    sd.spec = L.w;
+    sd.kofp = L.tab;
+    sd.pitch = G.sp.pitch;
     sten[v] = sd;
     red[v] = ReduceDesc{L.ctrl, L.partS, L.nbS, L.partF, L.nbF};
   }
@@ -1022,7 +1048,7 @@ size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
     std::vector<size_t> offs;
     BatchPlan plan;
     size_t hdr = 0;
-    return batch_workspace(p, count, false, &gs, &offs, &plan, &hdr);
+    return batch_workspace(p, count, 0, &gs, &offs, &plan, &hdr);
   }
   Geometry g;
   size_t total = 0;

@@ -268,8 +268,14 @@ hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *k
 struct BatchStencilDesc {
   AdmmStencilArgs a;
   float *nu[2];
-  StencilPlan pl;
+  StencilPlan pl;      // tiled plan, or stencil_r2c_plan for the fused stencil
+  float2 *spec;        // fused stencil: the x-update's spectrum (kofp order,
+  const int *kofp;     // rows `pitch` apart)
+  int pitch;
 };
+// The fused stencil over (volume, tile) items of volumes with row length M.
+hipError_t admm_stencil_r2c_batch(int M, const BatchStencilDesc *descs, const int2 *items,
+                                  int nitems, int k, bool fp64, bool aniso, hipStream_t st);
 hipError_t admm_stencil_batch(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
                               bool fp64, bool aniso, hipStream_t st);
 hipError_t theta_from_nu(const float *nu, float *theta, int S, int N, int M, float thr,

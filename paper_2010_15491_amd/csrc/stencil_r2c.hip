@@ -42,24 +42,23 @@ struct SRGeom {
   static_assert(H * TP * 2 <= XPLANE, "the FFT buffer fits one x plane buffer");
 };
 
+// Tile b of the plan; the residual sums go to partial slot `slot`.
 template <int M, typename Acc, bool ANISO>
-__global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a, StencilPlan pl,
-                                                               float2 *__restrict__ spec,
-                                                               const int *__restrict__ kofp,
-                                                               int pitch,
-                                                               const float2 *__restrict__ twh,
-                                                               const float2 *__restrict__ twm) {
+__device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const StencilPlan &pl,
+                                                 float2 *__restrict__ spec,
+                                                 const int *__restrict__ kofp, int pitch,
+                                                 const float2 *__restrict__ twh,
+                                                 const float2 *__restrict__ twm, int b,
+                                                 int slot) {
   using G = SRGeom<M>;
   constexpr int CH = G::CH, H = G::H, MH = G::MH, XPLANE = G::XPLANE, XPT = G::XPT;
   constexpr int FPT = G::FPT, TP = G::TP;
-  if (a.done && *a.done) return;
   __shared__ float xs[3][XPLANE];
   __shared__ float fw[G::FPLANE], fd[G::FPLANE], fu[G::FPLANE];  // n-components
   __shared__ float2 stw[H], stwm[MH];
   __shared__ int sperm[MH];
   __shared__ Acc sh[6 * 4];
 
-  const int b = xcd_tile(blockIdx.x, pl.blocks);
   const int S = a.S, N = a.N;
   const long NT = (long)S * N * M;
   const long plane = (long)N * M;
@@ -281,8 +280,37 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a
   block_reduce_n<Acc>(acc_t, 6, sh);
   if (tid == 0) {
     Acc *p = reinterpret_cast<Acc *>(a.part);
-    for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + blockIdx.x] = acc_t[q];
+    for (int q = 0; q < 6; ++q) p[(long)q * pl.blocks + slot] = acc_t[q];
   }
+}
+
+template <int M, typename Acc, bool ANISO>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c(AdmmStencilArgs a, StencilPlan pl,
+                                                               float2 *__restrict__ spec,
+                                                               const int *__restrict__ kofp,
+                                                               int pitch,
+                                                               const float2 *__restrict__ twh,
+                                                               const float2 *__restrict__ twm) {
+  if (a.done && *a.done) return;
+  stencil_r2c_body<M, Acc, ANISO>(a, pl, spec, kofp, pitch, twh, twm,
+                                  xcd_tile(blockIdx.x, pl.blocks), blockIdx.x);
+}
+
+// Batch: item (volume, tile) of the volumes with row length M; iteration k
+// reads nu[(k-1)&1] and writes nu[k&1].
+template <int M, typename Acc, bool ANISO>
+__global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c_batch(
+    const BatchStencilDesc *__restrict__ descs, const int2 *__restrict__ items, int k,
+    const float2 *__restrict__ twh, const float2 *__restrict__ twm) {
+  const int2 it = items[blockIdx.x];
+  const BatchStencilDesc d = descs[it.x];
+  if (d.a.done && *d.a.done) return;
+  AdmmStencilArgs a = d.a;
+  // A select, not an index into the local copy (which would put it in scratch).
+  float *const nu0 = d.nu[0], *const nu1 = d.nu[1];
+  a.nu_in = (k & 1) ? nu0 : nu1;
+  a.nu_out = (k & 1) ? nu1 : nu0;
+  stencil_r2c_body<M, Acc, ANISO>(a, d.pl, d.spec, d.kofp, d.pitch, twh, twm, it.y, it.y);
 }
 
 #define SR3D_STENCIL_R2C_M(X) X(64) X(128) X(192) X(256) X(384) X(512)
@@ -332,6 +360,34 @@ static void launch_sr(const AdmmStencilArgs &a, const StencilPlan &pl, float2 *s
                       const int *kofp, int pitch, bool fp64, hipStream_t st) {
   if (a.aniso) launch_sr_t<M, true>(a, pl, spec, kofp, pitch, fp64, st);
   else launch_sr_t<M, false>(a, pl, spec, kofp, pitch, fp64, st);
+}
+
+template <int M, bool ANISO>
+static void launch_srb_t(const BatchStencilDesc *descs, const int2 *items, int nitems, int k,
+                         bool fp64, hipStream_t st) {
+  const float2 *twh = twiddles(M / 2), *twm = twiddles(M);
+  if (fp64)
+    hipLaunchKernelGGL((k_admm_stencil_r2c_batch<M, double, ANISO>), dim3(nitems), dim3(kThreads),
+                       0, st, descs, items, k, twh, twm);
+  else
+    hipLaunchKernelGGL((k_admm_stencil_r2c_batch<M, float, ANISO>), dim3(nitems), dim3(kThreads),
+                       0, st, descs, items, k, twh, twm);
+}
+
+hipError_t admm_stencil_r2c_batch(int M, const BatchStencilDesc *descs, const int2 *items,
+                                  int nitems, int k, bool fp64, bool aniso, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  if (!stencil_r2c_supported(M) || !twiddles(M) || !twiddles(M / 2)) return hipErrorInvalidValue;
+  switch (M) {
+#define SR3D_CASE(L)                                                        \
+  case L:                                                                   \
+    if (aniso) launch_srb_t<L, true>(descs, items, nitems, k, fp64, st);   \
+    else launch_srb_t<L, false>(descs, items, nitems, k, fp64, st);        \
+    break;
+    SR3D_STENCIL_R2C_M(SR3D_CASE)
+#undef SR3D_CASE
+  }
+  return hipGetLastError();
 }
 
 hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *kofp, int pitch,

@@ -561,11 +561,13 @@ def test_wavelet_l1_resume_graph_and_tolerance_stop():
                                             levels=levels).x) < TOL
 
 
-@pytest.mark.parametrize("unfused", [False, True])
-def test_batch_mixes_fused_and_unfused_volumes(unfused):
+@pytest.mark.parametrize("extra", [0, 0x20, 0x40])
+def test_batch_mixes_fused_and_unfused_volumes(extra):
+    """Default (fused x-update, fused stencil where m allows), SR3D_UNFUSED and
+    SR3D_SEPARATE_R2C, over volumes that take different kernels."""
     cases = [((8, 32, 32), (2, 2, 2)), ((32, 32, 32), (2, 2, 2)), ((16, 12, 12), (3, 4, 2)),
-             ((24, 6, 8), (4, 3, 1))]
-    flags = sr3d.FP64_REDUCE | (sr3d.UNFUSED if unfused else 0)
+             ((24, 6, 8), (4, 3, 1)), ((16, 8, 64), (2, 2, 2)), ((32, 6, 128), (2, 2, 2))]
+    flags = sr3d.FP64_REDUCE | extra
     probs, refs = [], []
     for i, (shape, rate) in enumerate(cases):
         p = phantom.make_problem(shape, rate, 1.0, 0.02, 300 + i, n_ellipsoids=6)
