@@ -103,8 +103,8 @@ typedef struct {
                                   (same result up to FP32 rounding; for testing) */
 #define SR3D_SEPARATE_R2C 0x40 /* with the fused x-update: run the stencil and the m-axis
                                   R2C of the next x-update as separate kernels even where the
-                                  row length admits the fused stencil (64, 128, 192, 256,
-                                  384, 512); same bits, for testing */
+                                  row length admits the fused stencil (64, 128, 192, 256);
+                                  same bits, for testing */
 #define SR3D_TV_ANISO    0x80  /* anisotropic TV, lambda sum_j ||(L x)_j||_1, instead of the
                                   isotropic sum_j ||(L x)_j||_2: one of the other regularisers
                                   the same x-step serves (Sec. III-B). Step 5b becomes a soft

@@ -313,7 +313,11 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c_batch(
   stencil_r2c_body<M, Acc, ANISO>(a, d.pl, d.spec, d.kofp, d.pitch, twh, twm, it.y, it.y);
 }
 
-#define SR3D_STENCIL_R2C_M(X) X(64) X(128) X(192) X(256) X(384) X(512)
+// Row lengths where the fused kernel is faster than the tiled stencil and
+// the separate R2C together. Longer rows need 3 or 4 points per lane and 200+
+// VGPRs (one or two wavefronts per SIMD), and measured slower: 304 against
+// 200 us at m = 384, 890 against 588 us at m = 512.
+#define SR3D_STENCIL_R2C_M(X) X(64) X(128) X(192) X(256)
 
 bool stencil_r2c_supported(int M) {
   switch (M) {
@@ -332,7 +336,7 @@ StencilPlan stencil_r2c_plan(int S, int N, int M) {
   p.tiles_n = (N + SR_ROWS - 1) / SR_ROWS;
   // One round of workgroups over the 256 CUs at the occupancy the row
   // length allows (registers and LDS grow with M), 2..32 planes each.
-  const long target = M <= 128 ? 1024 : M <= 256 ? 768 : 512;
+  const long target = M <= 128 ? 1024 : 768;
   long L = ((long)S * p.tiles_n + target - 1) / target;
   if (L < 2) L = 2;
   if (L > 32) L = 32;

@@ -385,8 +385,9 @@ def test_fused_and_unfused_x_update_match_oracle(shape, rate):
     assert np.isclose(sf.objective, O.tv_objective(host(xf), y, psf, rate, LAM_TV), rtol=1e-4)
 
 
-# Row lengths the stencil with the fused m-axis R2C takes (64 .. 512), with
-# n-lengths that leave a ragged last tile of rows (n = 1, 2, 3, 6) or none.
+# Row lengths the stencil with the fused m-axis R2C takes (64 .. 256), with
+# n-lengths that leave a ragged last tile of rows (n = 1, 2, 3, 6) or none;
+# m = 384 and 512 take the separate kernels whatever the flags.
 ROW_CASES = [
     ((16, 6, 64), (2, 2, 2)),
     ((24, 12, 64), (1, 3, 3)),
