@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import tempfile
 import time
@@ -70,8 +71,23 @@ def alg_bytes_per_voxel(stage, hr, rate):
 
 
 def kernel_source_sha(path):
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """SHA-256 (16 hex digits) over a kernel's source file and, transitively,
+    the local headers it includes (`#include "name"` in the same folder)."""
+    h, seen, todo = hashlib.sha256(), set(), [path]
+    while todo:
+        rel = todo.pop(0)
+        if rel in seen:
+            continue
+        seen.add(rel)
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            text = f.read()
+        h.update(rel.encode() + b"\0" + text)
+        folder = os.path.dirname(rel)
+        for m in re.finditer(rb'^\s*#\s*include\s+"([^"]+)"', text, re.M):
+            inc = os.path.join(folder, m.group(1).decode())
+            if os.path.exists(os.path.join(ROOT, inc)):
+                todo.append(inc)
+    return h.hexdigest()[:16]
 
 
 def traffic_for(stage):
