@@ -447,20 +447,20 @@ hipError_t tv_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   return theta0_spectrum(g, L, st);
 }
 
-// Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2]. The
-// stopping test of an iteration runs in an extra workgroup of the next
-// iteration's first launch (fused path, not the first iteration of an
-// enqueued chunk: `merged`), or in its own launch at the end of a chunk
-// (`last`), so the host sees complete statistics after every chunk.
 // One iteration of the wavelet form: x-step by the Tikhonov fold (A = mu,
-// xbar in theta), then W, steps 5b/5c and W^T back into theta.
+// xbar in theta), then W, steps 5b/5c and W^T back into theta. On the fused
+// path the stopping test is carried by the next iteration's R2C as for TV.
 hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
-                             float *const nu[2], int k, bool fp64, hipStream_t st) {
+                             float *const nu[2], int k, bool fp64, hipStream_t st, bool merged,
+                             bool last) {
   const int *done = &L.ctrl->done;
   hipError_t e;
+  const bool carry = L.fused && g.M > 1;
   if (L.fused) {
     const int *kofp = L.tab, *posk = L.tab + g.Mh;
-    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st)))
+    const RedArgs red{L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64 ? 1 : 0};
+    if ((e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st,
+                              carry && merged ? &red : nullptr)))
       return e;
     prof_begin(kStSolveS, st);
     e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
@@ -491,12 +491,18 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
   }
   prof_end(st);
   if (e) return e;
+  if (carry && !last) return hipSuccess;  // reduced by the next iteration's first launch
   return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
 }
 
+// Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2]. The
+// stopping test of an iteration runs in an extra workgroup of the next
+// iteration's first launch (fused path, not the first iteration of an
+// enqueued chunk: `merged`), or in its own launch at the end of a chunk
+// (`last`), so the host sees complete statistics after every chunk.
 hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
                         int k, bool fp64, hipStream_t st, bool merged, bool last) {
-  if (L.haar) return wavelet_iteration(g, L, p, nu, k, fp64, st);
+  if (L.haar) return wavelet_iteration(g, L, p, nu, k, fp64, st, merged, last);
   const int *done = &L.ctrl->done;
   hipError_t e;
   // The iteration's first launch can carry the previous reduction: the R2C
