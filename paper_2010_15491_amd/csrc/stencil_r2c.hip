@@ -314,9 +314,10 @@ __global__ __launch_bounds__(kThreads) void k_admm_stencil_r2c_batch(
 }
 
 // Row lengths where the fused kernel is faster than the tiled stencil and
-// the separate R2C together. Longer rows need 3 or 4 points per lane and 200+
-// VGPRs (one or two wavefronts per SIMD), and measured slower: 304 against
-// 200 us at m = 384, 890 against 588 us at m = 512.
+// the separate R2C together. Longer rows hold 6 or 8 points per lane and
+// plane, 222 VGPRs at m = 384 and 256 plus 19 AGPRs at m = 512 (two and one
+// wavefronts per SIMD), and measured slower: 304 against 200 us at m = 384,
+// 890 against 588 us at m = 512.
 #define SR3D_STENCIL_R2C_M(X) X(64) X(128) X(192) X(256)
 
 bool stencil_r2c_supported(int M) {
