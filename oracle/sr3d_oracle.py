@@ -43,8 +43,8 @@ __all__ = [
     "grad", "grad_adjoint", "shrink", "shrink_aniso", "tikhonov", "tikhonov_objective",
     "haar3", "haar3_inverse", "haar_detail_mask", "shrink_detail", "wavelet_objective",
     "admm_wavelet",
-    "x_update", "AdmmResult", "admm_tv", "min_norm_dual", "tv_objective", "data_term", "psnr",
-    "rel_l2",
+    "x_update", "AdmmResult", "stopping_residuals", "admm_tv", "min_norm_dual", "tv_objective",
+    "data_term", "rel_l2",
 ]
 
 def _cpu_share():
@@ -324,6 +324,25 @@ def _rel(num, den):
     return num / den if den > 0 else float("inf")
 
 
+def stopping_residuals(Kx, u, u_new, d_new, adjoint, mu):
+    """Relative primal and dual residuals of the stopping rule.
+
+    Algorithm 1 names a stopping criterion without defining it; the reading
+    taken is the relative residuals of the ADMM reference the paper cites
+    (primal r = K x - u', dual s = mu K^T (u' - u)) with no absolute term, for
+    the split K x = u (K = L for TV, the Haar transform W for the wavelet
+    regulariser; ``adjoint`` applies K^T):
+        primal = ||K x - u'|| / max(||K x||, ||u'||),
+        dual   = mu ||K^T (u' - u)|| / (mu ||K^T d'||).
+    A zero denominator gives inf (not converged).
+    """
+    r_norm = float(np.sqrt(np.sum((Kx - u_new) ** 2)))
+    s_norm = mu * float(np.sqrt(np.sum(adjoint(u_new - u) ** 2)))
+    pri_den = max(float(np.sqrt(np.sum(Kx * Kx))), float(np.sqrt(np.sum(u_new * u_new))))
+    dual_den = mu * float(np.sqrt(np.sum(adjoint(d_new) ** 2)))
+    return _rel(r_norm, pri_den), _rel(s_norm, dual_den)
+
+
 def min_norm_dual(x0, y, psf, rate, mu):
     """Dual warm start (an extension, not in the paper): the minimum-norm d with
     mu L^T d = H^T D^T (y - D H x0) - (its mean), i.e. d = L phi,
@@ -351,8 +370,9 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
           x = F^H X with X from ``x_update``.
       5b  nu = L x + d; u' = shrink(nu, lam/mu).
       5c  d' = d + (L x - u').
-    Stopping rule (tol > 0): ||L x - u'|| <= tol max(||L x||, ||u'||) and
-    mu ||L^T (u' - u)|| <= tol mu ||L^T d'||. tol = 0 runs exactly max_iter.
+    Stopping rule (tol > 0, ``stopping_residuals``): ||L x - u'|| <= tol
+    max(||L x||, ||u'||) and mu ||L^T (u' - u)|| <= tol mu ||L^T d'||.
+    tol = 0 runs exactly max_iter.
     Output: x of the last x-update (step "Output").
     """
     y = np.asarray(y, np.float64)
@@ -384,11 +404,7 @@ def admm_tv(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
         u_new = prox(nu, thr)
         d_new = d + (Lx - u_new)
 
-        r_norm = float(np.sqrt(np.sum((Lx - u_new) ** 2)))
-        s_norm = mu * float(np.sqrt(np.sum(grad_adjoint(u_new - u) ** 2)))
-        pri_den = max(float(np.sqrt(np.sum(Lx * Lx))), float(np.sqrt(np.sum(u_new * u_new))))
-        dual_den = mu * float(np.sqrt(np.sum(grad_adjoint(d_new) ** 2)))
-        prel, drel = _rel(r_norm, pri_den), _rel(s_norm, dual_den)
+        prel, drel = stopping_residuals(Lx, u, u_new, d_new, grad_adjoint, mu)
         if record:
             hist.append((prel, drel))
         if callback is not None:
@@ -482,7 +498,7 @@ def admm_wavelet(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, levels=1, re
     Loop: 5a x = argmin 1/2||y - DHx||^2 + mu/2 ||W x - u + d||^2, i.e.
     ``tikhonov(y, psf, rate, mu/2, xbar=W^T(u - d))``; 5b nu = W x + d,
     u' = shrink_detail(nu, lam/mu); 5c d' = d + (W x - u').
-    Stopping rule as admm_tv with L^T -> W^T: ||W^T z|| = ||z||.
+    Stopping rule as admm_tv with L -> W (``stopping_residuals``).
     """
     y = np.asarray(y, np.float64)
     hr = hr_shape_of(y.shape, rate)
@@ -502,11 +518,8 @@ def admm_wavelet(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, levels=1, re
         nu = c + d
         u_new = shrink_detail(nu, thr, mask)
         d_new = d + (c - u_new)
-        r_norm = float(np.sqrt(np.sum((c - u_new) ** 2)))
-        s_norm = mu * float(np.sqrt(np.sum((u_new - u) ** 2)))
-        pri_den = max(float(np.sqrt(np.sum(c * c))), float(np.sqrt(np.sum(u_new * u_new))))
-        dual_den = mu * float(np.sqrt(np.sum(d_new * d_new)))
-        prel, drel = _rel(r_norm, pri_den), _rel(s_norm, dual_den)
+        prel, drel = stopping_residuals(c, u, u_new, d_new,
+                                        lambda z: haar3_inverse(z, levels), mu)
         if record:
             hist.append((prel, drel))
         if callback is not None:
@@ -522,13 +535,6 @@ def admm_wavelet(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, levels=1, re
 # ---------------------------------------------------------------------------
 # Metrics
 # ---------------------------------------------------------------------------
-
-def psnr(x, ref):
-    """Peak signal-to-noise ratio in dB, peak = max |ref|."""
-    mse = float(np.mean((np.asarray(x, np.float64) - ref) ** 2))
-    peak = float(np.max(np.abs(ref)))
-    return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
-
 
 def rel_l2(a, b):
     """||a - b|| / ||b|| in float64."""

@@ -604,3 +604,136 @@ def test_min_norm_dual_solves_stationarity_with_least_norm():
     d_ref = np.linalg.pinv(mu * L.T) @ r
     d = O.min_norm_dual(x0, y, psf, rate, mu).reshape(-1)
     assert np.allclose(d, d_ref, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Stopping rule. Algorithm 1 names a stopping criterion without defining it;
+# the reading is the relative primal/dual residuals of the ADMM reference the
+# paper cites. Pinned with explicit matrices K (= L or the Haar W) on random
+# inputs, where either term of max(||Kx||, ||u'||) can be the larger, and on
+# the recorded history of real runs, with (u', d') recomputed from steps 5b/5c.
+# ---------------------------------------------------------------------------
+
+
+def _dense_residuals(K, kx, u, u1, d1, mu):
+    """Relative residuals from flattened vectors and an explicit matrix K."""
+    r = np.linalg.norm(kx - u1)
+    s = mu * np.linalg.norm(K.T @ (u1 - u))
+    pden = max(np.linalg.norm(kx), np.linalg.norm(u1))
+    dden = mu * np.linalg.norm(K.T @ d1)
+    return r / pden, s / dden
+
+
+@pytest.mark.parametrize("u_scale", [0.3, 3.0])
+def test_stopping_residuals_match_dense_operators(u_scale):
+    """u_scale 3 makes ||u'|| the larger denominator term, 0.3 ||Kx||."""
+    rng = np.random.default_rng(40)
+    shape, mu = (4, 5, 6), 0.07
+    L = dense_L(shape)
+    kx, u, u1, d1 = (rng.standard_normal((3,) + shape) for _ in range(4))
+    u1 = u_scale * u1
+    assert (np.linalg.norm(u1) > np.linalg.norm(kx)) == (u_scale > 1)
+    got = O.stopping_residuals(kx, u, u1, d1, O.grad_adjoint, mu)
+    ref = _dense_residuals(L, kx.ravel(), u.ravel(), u1.ravel(), d1.ravel(), mu)
+    assert np.allclose(got, ref, rtol=1e-12)
+    levels, wshape = 2, (4, 4, 8)
+    W = _dense_haar(wshape, levels)
+    kx, u, u1, d1 = (rng.standard_normal(wshape) for _ in range(4))
+    u1 = u_scale * u1
+    got = O.stopping_residuals(kx, u, u1, d1, lambda z: O.haar3_inverse(z, levels), mu)
+    ref = _dense_residuals(W, kx.ravel(), u.ravel(), u1.ravel(), d1.ravel(), mu)
+    assert np.allclose(got, ref, rtol=1e-12)
+
+
+def _check_history(res, recs):
+    assert len(res.history) == len(recs) == res.iters
+    h = np.array(res.history)
+    # primal = 1 exactly when u' = 0: a trivial run would pin nothing
+    assert np.all(np.isfinite(h) & (h > 0)) and np.all(h[:, 0] < 1)
+    assert np.allclose(np.array(res.history), np.array(recs), rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("aniso,warm", [(False, False), (True, False), (False, True)])
+def test_admm_tv_history_is_the_dense_stopping_rule(aniso, warm):
+    """Every recorded (primal, dual) pair equals the rule evaluated with the
+    dense L on that iteration's x, old (u, d) and new (u', d'); (u', d') are
+    steps 5b/5c of nu = Lx + d. Along the way ||u'|| <= ||Lx|| (since
+    ||d_j|| <= lam/mu), so the primal denominator is ||Lx||."""
+    shape = (8, 8, 8)
+    y, psf, rate = _toy_problem(seed=27)
+    lam, mu = 2e-3, 0.05
+    L = dense_L(shape)
+    x0 = O.tikhonov(y, psf, rate, 1e-2) if warm else None
+    recs = []
+
+    def cb(it, x, u, d, u1, d1):
+        lx = L @ x.ravel()
+        nu = (lx + d.ravel()).reshape((3,) + shape)
+        prox = O.shrink_aniso(nu, lam / mu) if aniso else O.shrink(nu, lam / mu)
+        assert np.allclose(u1, prox, rtol=0, atol=1e-13)
+        assert np.allclose(d1, nu - prox, rtol=0, atol=1e-13)
+        assert np.linalg.norm(u1) <= np.linalg.norm(lx) * (1 + 1e-12)
+        recs.append(_dense_residuals(L, lx, u.ravel(), u1.ravel(), d1.ravel(), mu))
+
+    res = O.admm_tv(y, psf, rate, lam, mu, 25, x0=x0, warm_dual=warm, aniso=aniso,
+                    record=True, callback=cb)
+    _check_history(res, recs)
+    assert (res.primal_rel, res.dual_rel) == res.history[-1]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_admm_wavelet_history_is_the_dense_stopping_rule(levels):
+    shape = (4, 4, 8)
+    y, psf, rate = _toy_problem(shape=shape, rate=(1, 1, 2), sigma=0.5, seed=28)
+    lam, mu = 2e-3, 0.05
+    W = _dense_haar(shape, levels)
+    mask = O.haar_detail_mask(shape, levels)
+    recs = []
+
+    def cb(it, x, u, d, u1, d1):
+        wx = W @ x.ravel()
+        nu = (wx + d.ravel()).reshape(shape)
+        soft = np.sign(nu) * np.maximum(np.abs(nu) - lam / mu, 0.0)
+        assert np.allclose(u1, np.where(mask, soft, nu), rtol=0, atol=1e-13)
+        assert np.allclose(d1, nu - u1, rtol=0, atol=1e-13)
+        recs.append(_dense_residuals(W, wx, u.ravel(), u1.ravel(), d1.ravel(), mu))
+
+    res = O.admm_wavelet(y, psf, rate, lam, mu, 25, levels=levels, record=True, callback=cb)
+    _check_history(res, recs)
+
+
+@pytest.mark.parametrize("tol,tol_dual", [(2e-2, None), (1e-3, 5e-2)])
+def test_admm_stops_at_first_iteration_meeting_the_rule(tol, tol_dual):
+    """The run stops at the first iteration whose recorded residuals meet the
+    tolerances, and not before; a tol = 0 run of the same length records the
+    same history."""
+    y, psf, rate = _toy_problem(seed=29)
+    lam, mu = 2e-3, 0.05
+    full = O.admm_tv(y, psf, rate, lam, mu, 400, record=True)
+    td = tol_dual or tol
+    hits = [i for i, (p, q) in enumerate(full.history) if p <= tol and q <= td]
+    assert hits, "tolerance never met; pick a looser one"
+    res = O.admm_tv(y, psf, rate, lam, mu, 400, tol=tol, tol_dual=tol_dual, record=True)
+    assert res.converged and res.iters == hits[0] + 1
+    assert res.history == full.history[: res.iters]
+    short = O.admm_tv(y, psf, rate, lam, mu, hits[0], tol=tol, tol_dual=tol_dual)
+    assert not short.converged and short.iters == hits[0]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_wavelet_objective_matches_dense(levels):
+    """1/2||y - DHx||^2 + lam sum |detail rows of W applied to x|, with the
+    approximation rows of the dense W found on their own: they are the rows
+    with a non-zero sum (every detail row is orthogonal to the constants)."""
+    rng = np.random.default_rng(31)
+    shape, rate, lam = (4, 4, 8), (2, 2, 2), 0.37
+    W = _dense_haar(shape, levels)
+    approx = np.abs(W.sum(axis=1)) > 1e-9
+    assert approx.sum() == W.shape[0] // 8 ** levels
+    psf = rand_psf(rng, (3, 3, 3))
+    x = rng.standard_normal(shape)
+    y = rng.standard_normal(O.lr_shape_of(shape, rate))
+    H, D = dense_H(psf, shape), dense_D(shape, rate)
+    ref = 0.5 * np.sum((y.ravel() - D @ H @ x.ravel()) ** 2) \
+        + lam * np.sum(np.abs(W[~approx] @ x.ravel()))
+    assert np.isclose(O.wavelet_objective(x, y, psf, rate, lam, levels), ref, rtol=1e-12)
