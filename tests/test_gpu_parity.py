@@ -4,6 +4,8 @@ Inputs are seeded synthetic phantoms; both sides get the same float32-rounded
 y, PSF and x0. Bar for the FP32 path: rel-L2 <= 1e-5 against FP64.
 """
 
+import time
+
 import numpy as np
 import pytest
 
@@ -15,6 +17,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = 1e-5
+# Element-wise bar: max |x - x_ref| <= ELEM * max |x_ref|. A global rel-L2
+# alone would let a large error at a few voxels pass (at 256^3 one voxel is
+# 1/4096 of the norm); this bounds every voxel by the same 1e-5 taken
+# relative to the volume's peak.
+ELEM = 1e-5
 
 
 def dev(a):
@@ -29,6 +36,26 @@ def host(t):
 
 def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def progress(request, msg):
+    """Prints a progress line past pytest's output capture (long oracle runs)."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    with capman.global_and_fixture_disabled():
+        print(msg, flush=True)
+
+
+def close(got, ref, tol=TOL, elem=ELEM):
+    """Asserts rel-L2(got, ref) <= tol and max|got - ref| <= elem * max|ref|;
+    returns the rel-L2 error."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    err = O.rel_l2(got, ref)
+    peak = float(np.abs(ref).max())
+    worst = float(np.abs(got - ref).max())
+    assert err <= tol, f"rel-L2 {err:.3e} > {tol:.0e}"
+    assert worst <= elem * peak, f"max abs error {worst:.3e} > {elem:.0e} x peak {peak:.3e}"
+    return err
 
 
 def problem(shape, rate, sigma, noise, seed, texture=False, n_ell=12):
@@ -93,7 +120,7 @@ def test_autotune_runs_and_keeps_results_correct():
     y, psf, _ = problem((32, 48, 64), (2, 2, 4), 1.2, 0.02, 3)
     x, st = sr3d.tv_admm(dev(y), dev(psf), (2, 2, 4), LAM_TV, MU, 5)
     ref = O.admm_tv(y, psf, (2, 2, 4), LAM_TV, MU, 5)
-    assert O.rel_l2(host(x), ref.x) < TOL
+    close(host(x), ref.x)
 
 
 def test_rfft3d_matches_bruteforce_dft():
@@ -127,7 +154,7 @@ def test_degrade_matches_oracle(shape, rate, kshape):
     psf = f32(psf)
     got = host(sr3d.degrade(dev(x), dev(psf), rate))
     ref = O.degrade(x, psf, rate)
-    assert O.rel_l2(got, ref) < 2e-6
+    close(got, ref, tol=2e-6)
 
 
 def test_tikhonov_config_32cube():
@@ -135,7 +162,7 @@ def test_tikhonov_config_32cube():
     y, psf, _ = problem((32, 32, 32), (2, 2, 2), 1.0, 0.01, 0)
     x = host(sr3d.tikhonov(dev(y), dev(psf), (2, 2, 2), 1e-3))
     ref = O.tikhonov(y, psf, (2, 2, 2), 1e-3)
-    assert O.rel_l2(x, ref) < TOL
+    close(x, ref)
 
 
 @pytest.mark.parametrize("shape,rate,kshape,lam", [
@@ -155,9 +182,9 @@ def test_tikhonov_matches_oracle_with_xbar(shape, rate, kshape, lam):
     xbar = f32(rng.standard_normal(shape) * 0.1)
     got = host(sr3d.tikhonov(dev(y), dev(psf), rate, lam, xbar=dev(xbar)))
     ref = O.tikhonov(y, psf, rate, lam, xbar)
-    assert O.rel_l2(got, ref) < TOL
+    close(got, ref)
     got0 = host(sr3d.tikhonov(dev(y), dev(psf), rate, lam))
-    assert O.rel_l2(got0, O.tikhonov(y, psf, rate, lam)) < TOL
+    close(got0, O.tikhonov(y, psf, rate, lam))
 
 
 # ---------------------------------------------------------------------------
@@ -181,11 +208,11 @@ def test_tv_admm_fixed_iterations_match_oracle(shape, rate, sigma, iters):
     x = host(x)
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, iters)
     assert st.iters == iters and not st.converged
-    err = O.rel_l2(x, ref.x)
-    print(f"{shape} {rate} {iters} it: rel-L2 {err:.3e}")
-    assert err < TOL
-    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-2)
-    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=5e-2)
+    err = close(x, ref.x)
+    print(f"{shape} {rate} {iters} it: rel-L2 {err:.3e}, primal {st.primal_rel:.4e} vs "
+          f"{ref.primal_rel:.4e}, dual {st.dual_rel:.4e} vs {ref.dual_rel:.4e}")
+    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
 
 
 def test_tv_admm_warm_start_x0_matches_oracle():
@@ -194,7 +221,7 @@ def test_tv_admm_warm_start_x0_matches_oracle():
     x0 = f32(O.tikhonov(y, psf, rate, 1e-3))
     x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 25, x0=dev(x0))
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 25, x0=x0)
-    assert O.rel_l2(host(x), ref.x) < TOL
+    close(host(x), ref.x)
 
 
 def test_tv_admm_dual_warm_start_matches_oracle():
@@ -204,8 +231,8 @@ def test_tv_admm_dual_warm_start_matches_oracle():
     x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10, x0=dev(x0),
                          flags=sr3d.FP64_REDUCE | sr3d.WARM_DUAL)
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 10, x0=x0, warm_dual=True)
-    assert O.rel_l2(host(x), ref.x) < TOL
-    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=5e-2)
+    close(host(x), ref.x)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
 
 
 def test_tv_admm_separate_dual_tolerance_matches_oracle():
@@ -253,7 +280,7 @@ def test_tv_admm_state_invariants_and_resume():
     x20, _ = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 20)
     assert torch.equal(x20r, x20)
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 20)
-    assert O.rel_l2(host(x20), ref.x) < TOL
+    close(host(x20), ref.x)
 
 
 def test_fp32_and_fp64_reductions_leave_x_unchanged_and_graph_replay():
@@ -308,8 +335,8 @@ def test_batch_matches_single_solves():
     for x, st, ref, q in zip(xs, sts, refs, probs):
         single, _ = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 15)
         assert st.iters == 15
-        assert O.rel_l2(host(x), host(single)) < 1e-6
-        assert O.rel_l2(host(x), ref) < TOL
+        close(host(x), host(single), tol=1e-6)
+        close(host(x), ref)
 
 
 @pytest.mark.parametrize("graph", [False, True])
@@ -332,7 +359,7 @@ def test_batch_uneven_volumes_stop_like_single_solves(graph):
     assert len(set(iters)) > 1, iters  # volumes really stop at different iterations
     for x, st, (xs1, st1) in zip(xs, sts, singles):
         assert st.iters == st1.iters and st.converged == st1.converged
-        assert O.rel_l2(host(x), host(xs1)) < 1e-6
+        close(host(x), host(xs1), tol=1e-6)
 
 
 # ---------------------------------------------------------------------------
@@ -364,6 +391,10 @@ FUSE_CASES = [
     ((384, 8, 8), (2, 2, 4)),
     ((192, 24, 24), (2, 2, 2)),
     ((128, 32, 32), (4, 4, 2)),
+    # s = 96 at every compile-time group size (d = 8, 16, 32)
+    ((96, 24, 24), (2, 2, 2)),
+    ((96, 16, 16), (2, 2, 4)),
+    ((96, 32, 32), (4, 4, 2)),
 ]
 
 
@@ -376,10 +407,11 @@ def test_fused_and_unfused_x_update_match_oracle(shape, rate):
     xf, sf = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 8)
     xu, su = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 8,
                           flags=sr3d.FP64_REDUCE | sr3d.UNFUSED)
-    ef, eu = O.rel_l2(host(xf), ref.x), O.rel_l2(host(xu), ref.x)
+    ef, eu = close(host(xf), ref.x), close(host(xu), ref.x)
     print(f"{shape} {rate}: fused {ef:.2e}, unfused {eu:.2e}")
-    assert ef < TOL and eu < TOL
-    assert O.rel_l2(host(xf), host(xu)) < 1e-6
+    assert np.isclose(sf.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(sf.dual_rel, ref.dual_rel, rtol=1e-3)
+    close(host(xf), host(xu), tol=1e-6)
     assert np.isclose(sf.primal_rel, su.primal_rel, rtol=1e-4)
     assert np.isclose(sf.objective, su.objective, rtol=1e-5)
     assert np.isclose(sf.objective, O.tv_objective(host(xf), y, psf, rate, LAM_TV), rtol=1e-4)
@@ -417,7 +449,7 @@ def test_fused_stencil_r2c_matches_separate_kernels(shape, rate):
     print(f"{shape} {rate}: {O.rel_l2(host(xf), ref.x):.2e}")
     assert torch.equal(xf, xs) and torch.equal(xf, xg)
     assert sf.iters == ss.iters == sg.iters == 7
-    assert O.rel_l2(host(xf), ref.x) < TOL
+    close(host(xf), ref.x)
     # residual sums over a different tiling: equal up to FP32 summation order
     assert np.isclose(sf.primal_rel, ss.primal_rel, rtol=1e-4)
     assert np.isclose(sf.dual_rel, ss.dual_rel, rtol=1e-4)
@@ -436,7 +468,7 @@ def test_fused_stencil_r2c_tolerance_stop_matches_oracle():
         x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 200, tol=tol, flags=flags)
         assert ref.converged and st.converged and abs(st.iters - ref.iters) <= 1
         assert st.primal_rel <= tol and st.dual_rel <= tol
-        assert O.rel_l2(host(x), O.admm_tv(y, psf, rate, LAM_TV, MU, st.iters).x) < TOL
+        close(host(x), O.admm_tv(y, psf, rate, LAM_TV, MU, st.iters).x)
 
 
 # Anisotropic TV through the same x-step: fused stencil (m = 64, 128), tiled
@@ -458,9 +490,8 @@ def test_tv_aniso_matches_oracle(shape, rate, extra):
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 10, aniso=True)
     x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10,
                          flags=sr3d.FP64_REDUCE | sr3d.TV_ANISO | extra)
-    err = O.rel_l2(host(x), ref.x)
+    err = close(host(x), ref.x)
     print(f"{shape} {rate} flags+{extra:#x}: aniso rel-L2 {err:.2e}")
-    assert err < TOL
     assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
     assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
     assert np.isclose(st.objective, O.tv_objective(host(x), y, psf, rate, LAM_TV, aniso=True),
@@ -502,8 +533,8 @@ def test_tv_aniso_batch_matches_single_solves():
     for x, st, ref, q in zip(xs, sts, refs, probs):
         single, _ = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 9, flags=fl)
         assert st.iters == 9
-        assert O.rel_l2(host(x), host(single)) < 1e-6
-        assert O.rel_l2(host(x), ref) < TOL
+        close(host(x), host(single), tol=1e-6)
+        close(host(x), ref)
 
 
 # l1 of orthonormal 3D Haar details through the same x-step (Tikhonov fold).
@@ -528,9 +559,8 @@ def test_wavelet_l1_matches_oracle(shape, rate, levels, unfused):
     x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 10,
                          flags=sr3d.FP64_REDUCE | sr3d.REG_HAAR | sr3d.HAAR_LEVELS(levels)
                          | (sr3d.UNFUSED if unfused else 0))
-    err = O.rel_l2(host(x), ref.x)
+    err = close(host(x), ref.x)
     print(f"{shape} {rate} levels {levels} unfused {unfused}: rel-L2 {err:.2e}")
-    assert err < TOL
     assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
     assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
     assert np.isclose(st.objective, O.wavelet_objective(host(x), y, psf, rate, LAM_TV, levels),
@@ -552,14 +582,12 @@ def test_wavelet_l1_resume_graph_and_tolerance_stop():
     # warm start: nu0 = W x0
     x0 = f32(O.tikhonov(y, psf, rate, 1e-3))
     xw, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 6, x0=dev(x0), flags=fl)
-    assert O.rel_l2(host(xw), O.admm_wavelet(y, psf, rate, LAM_TV, MU, 6, x0=x0,
-                                             levels=levels).x) < TOL
+    close(host(xw), O.admm_wavelet(y, psf, rate, LAM_TV, MU, 6, x0=x0, levels=levels).x)
     tol = 1e-3
     ref = O.admm_wavelet(y, psf, rate, LAM_TV, MU, 300, tol=tol, levels=levels)
     x, st = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 300, tol=tol, flags=fl | sr3d.CHECK_INTERVAL(1))
     assert ref.converged and st.converged and abs(st.iters - ref.iters) <= 1
-    assert O.rel_l2(host(x), O.admm_wavelet(y, psf, rate, LAM_TV, MU, st.iters,
-                                            levels=levels).x) < TOL
+    close(host(x), O.admm_wavelet(y, psf, rate, LAM_TV, MU, st.iters, levels=levels).x)
 
 
 @pytest.mark.parametrize("extra", [0, 0x20, 0x40])
@@ -581,8 +609,8 @@ def test_batch_mixes_fused_and_unfused_volumes(extra):
     for x, st, ref, q in zip(xs, sts, refs, probs):
         single, s1 = sr3d.tv_admm(q["y"], q["psf"], q["rate"], LAM_TV, MU, 12, flags=flags)
         assert st.iters == 12
-        assert O.rel_l2(host(x), host(single)) < 1e-6
-        assert O.rel_l2(host(x), ref) < TOL
+        close(host(x), host(single), tol=1e-6)
+        close(host(x), ref)
 
 
 # ---------------------------------------------------------------------------
@@ -599,9 +627,8 @@ def test_full_size_256_first_iterations_and_invariants():
     Y, P = dev(y), dev(psf)
     x2, _ = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 2)
     ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 2)
-    err = O.rel_l2(host(x2), ref.x)
+    err = close(host(x2), ref.x)
     print(f"256^3 after 2 iterations: rel-L2 {err:.3e}")
-    assert err < TOL
     state = torch.zeros(3 * y.size * 8, device="cuda")
     x, st = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 200, tol=1e-4, state=state)
     nu = host(state).reshape((3,) + shape)
@@ -616,7 +643,63 @@ def test_full_size_256_first_iterations_and_invariants():
     xs, ss = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, flags=sr3d.FP64_REDUCE | sr3d.SEPARATE_R2C)
     xu, su = sr3d.tv_admm(Y, P, rate, LAM_TV, MU, 5, flags=sr3d.FP64_REDUCE | sr3d.UNFUSED)
     assert torch.equal(xf, xs)
-    assert O.rel_l2(host(xf), host(xu)) < 1e-6
+    close(host(xf), host(xu), tol=1e-6)
     for a_, b_ in ((sf, ss), (sf, su)):
         assert np.isclose(a_.primal_rel, b_.primal_rel, rtol=1e-4)
         assert np.isclose(a_.dual_rel, b_.dual_rel, rtol=1e-4)
+
+
+def test_batch_with_96x192x192_volumes_at_every_group_size():
+    """The batch workload's largest s = 96 volumes (96 x 192 x 192 at d = 8, 16
+    and 32) through sr3d_batch, each against the oracle: the fused x-update at
+    s = 96 for every compile-time group size and the batched fused stencil at
+    m = 192."""
+    cases = [((96, 192, 192), (4, 4, 2), 1.2), ((96, 192, 192), (2, 2, 4), 0.9),
+             ((96, 192, 192), (2, 2, 2), 1.6), ((64, 64, 64), (2, 2, 2), 1.0)]
+    probs, refs = [], []
+    for i, (shape, rate, sig) in enumerate(cases):
+        y, psf, _ = problem(shape, rate, sig, 0.02, 500 + i)
+        probs.append(dict(y=dev(y), psf=dev(psf), rate=rate, lam=LAM_TV, mu=MU, max_iter=10,
+                          tol=0.0))
+        refs.append(O.admm_tv(y, psf, rate, LAM_TV, MU, 10))
+    xs, sts = sr3d.batch(probs, flags=sr3d.FP64_REDUCE)
+    for (shape, rate, _), x, st, ref in zip(cases, xs, sts, refs):
+        assert st.iters == 10
+        err = close(host(x), ref.x)
+        print(f"batch {shape} {rate}: rel-L2 {err:.2e}")
+        assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+        assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
+
+
+@pytest.mark.timeout(1800)
+def test_full_size_256_benchmark_solve_matches_oracle(request):
+    """The benchmark's solve exactly (256^3, seed 1 with texture, d = 2x2x2,
+    sigma 1.5, lambda 2e-3, mu 5e-2, tol 1e-4, cap 200, FP64 reductions, the
+    default kernels) against the oracle's Algorithm 1 with the same stopping
+    rule: same iteration count and stop decision, x within the bar."""
+    shape, rate = (256, 256, 256), (2, 2, 2)
+    p = phantom.make_problem(shape, rate, 1.5, 0.02, 1, texture=True)
+    psf = f32(p["psf"])
+    y = f32(O.degrade(p["x_true"], psf, rate) + p["noise"])
+    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM_TV, MU, 200, tol=1e-4,
+                         flags=sr3d.FP64_REDUCE)
+    xg = host(x)
+    del x
+    progress(request, f"GPU 256^3 solve: {st.iters} iterations, converged {st.converged}; "
+                      "oracle running")
+    t0 = time.perf_counter()
+
+    def cb(it, *_):
+        if it % 20 == 0:
+            progress(request, f"oracle 256^3 iteration {it}/200, {time.perf_counter() - t0:.0f} s")
+
+    ref = O.admm_tv(y, psf, rate, LAM_TV, MU, 200, tol=1e-4, callback=cb)
+    err = close(xg, ref.x)
+    worst = float(np.abs(xg - ref.x).max() / np.abs(ref.x).max())
+    progress(request, f"256^3 x 200: rel-L2 {err:.3e}, max abs error / peak {worst:.3e}, "
+                      f"iters {st.iters}/{ref.iters}, primal {st.primal_rel:.5e} vs "
+                      f"{ref.primal_rel:.5e}, dual {st.dual_rel:.5e} vs {ref.dual_rel:.5e}")
+    assert st.iters == ref.iters and bool(st.converged) == ref.converged
+    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
+    assert np.isclose(st.objective, O.tv_objective(xg, y, psf, rate, LAM_TV), rtol=1e-5)
