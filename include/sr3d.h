@@ -16,8 +16,10 @@
  *
  * Ownership: the caller owns every pointer passed in (device memory unless
  * stated) and the workspace. The library owns only per-device twiddle tables
- * and a small pinned host block, created on first use and released by
- * sr3d_shutdown(). Inputs are read-only; outputs must not alias inputs.
+ * and the scratch of sr3d_tikhonov_noalloc (static device arrays, held until
+ * the process ends) and a small pinned host block, created on first use and
+ * released by sr3d_shutdown(). Inputs are read-only; outputs must not alias
+ * inputs.
  *
  * Streams: all work is enqueued on the caller's stream. Functions return
  * after enqueueing, except sr3d_tv_admm / sr3d_batch, which synchronise the
@@ -144,6 +146,25 @@ int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf
                   sr3d_dims psf_dims, const float *xbar, float lambda, float *x,
                   void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as sr3d_tikhonov, through the same kernels and with the same result
+ * bits, with no workspace argument. Its workspace is a static device array
+ * of SR3D_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the library runs on
+ * holds until the process ends; the call allocates nothing. A problem whose
+ * sr3d_workspace_size(SR3D_OP_TIKHONOV, ...) exceeds the array (e.g. more
+ * than a 128^3 HR volume) returns SR3D_ERR_WORKSPACE before any HIP call.
+ * The first call on a device looks up the array's address and uploads the
+ * FFT twiddle tables with a synchronous copy, so make it before any graph
+ * capture; later calls only enqueue kernels on `stream`. Every call on one
+ * GPU uses that GPU's one array, whose contents persist between calls (no
+ * part of it needs clearing: each buffer is written before it is read):
+ * calls that overlap on one GPU (other streams, other threads) race. */
+#define SR3D_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sr3d_tikhonov_noalloc(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf,
+                          sr3d_dims psf_dims, const float *xbar, float lambda, float *x,
+                          hipStream_t stream);
+
 /* 3D-FSR-l2-TV: Algorithm 1 (Sec. III-B). Initialisation u0, d0 from x0 by
  * steps 5b/5c with d = 0 (x0 = 0 gives u0 = d0 = 0). Each iteration runs the
  * x-update 5a through eq. (12) in the Fourier domain (the zero-frequency alias
@@ -254,7 +275,8 @@ void sr3d_profile_select(unsigned stage_mask);
 const char *sr3d_status_string(int status);
 /* Message describing the calling thread's last failed call ("" if none). */
 const char *sr3d_last_error(void);
-/* Releases twiddle tables and host staging on every device used. */
+/* Releases the host staging and forgets the per-device table addresses (the
+ * static device arrays themselves stay until the process ends). */
 void sr3d_shutdown(void);
 
 #ifdef __cplusplus

@@ -96,6 +96,13 @@ struct ProfScope {
 
 using namespace sr3d;
 
+// Workspace of sr3d_tikhonov_noalloc: a static device array (64 MiB, enough
+// for a 128^3 HR volume), held by every device the library runs on until the
+// process ends. In host code `scratch` is a host-side stand-in; its device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is handed to kernels.
+static __device__ __align__(256) char scratch[SR3D_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 int fail(int code, const std::string &msg) {
@@ -1043,6 +1050,55 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
   return SR3D_OK;
 }
 
+int check_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf,
+                   sr3d_dims psf_dims, const float *xbar, float lambda, const float *x,
+                   Geometry *g) {
+  int rc = check_geometry(hr, rate, &psf_dims, g);
+  if (rc) return rc;
+  if (!y || !psf || !x) return fail(SR3D_ERR_INVALID_ARG, "y, psf and x must be non-NULL");
+  if (!(lambda > 0.f) || !isfinite(lambda)) return fail(SR3D_ERR_INVALID_ARG, "lambda must be finite and > 0");
+  if (x == y || x == psf || (xbar && x == xbar)) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
+  return SR3D_OK;
+}
+
+// eq. (12): Lambda and Y by R2C, the per-group solve with A = 2 lambda and
+// K = conj(Lambda) Y + 2 lambda F xbar, one C2R. Every workspace buffer is
+// written before it is read, so nothing needs clearing.
+int tikhonov_run(const Geometry &g, const TikWs &L, const float *y, const float *psf,
+                 sr3d_dims psf_dims, const float *xbar, float lambda, float *x, hipStream_t st) {
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(pad_psf(psf, psf_dims.s, psf_dims.n, psf_dims.m, L.real, g.S, g.N, g.M, st), "pad psf");
+  SR3D_TRY(fft3d_forward(L.real, L.lam, g.S, g.N, g.M, nullptr, st), "fft Lambda");
+  SR3D_TRY(fft3d_forward(y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st), "fft y");
+  if (xbar) SR3D_TRY(fft3d_forward(xbar, L.w, g.S, g.N, g.M, nullptr, st), "fft xbar");
+  FoldArgs fa = make_fold(g);
+  fa.W = xbar ? L.w : nullptr; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+  fa.cw = 2.0f * lambda; fa.coefA = 2.0f * lambda; fa.tv = 0;
+  fa.partial = nullptr; fa.ctrl = nullptr; fa.done = nullptr;
+  SR3D_TRY(fold_solve(fa, false, st), "fold solve");
+  SR3D_TRY(fft3d_inverse(L.w2, x, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
+  return SR3D_OK;
+}
+
+std::mutex g_scratch_mu;
+char *g_scratch[64] = {nullptr};
+
+hipError_t scratch_address(char **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = reinterpret_cast<char *>(p);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1085,27 +1141,30 @@ int sr3d_tikhonov(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf
                   const float *xbar, float lambda, float *x, void *ws, size_t ws_bytes,
                   hipStream_t st) {
   Geometry g;
-  int rc = check_geometry(hr, rate, &psf_dims, &g);
+  int rc = check_tikhonov(hr, rate, y, psf, psf_dims, xbar, lambda, x, &g);
   if (rc) return rc;
-  if (!y || !psf || !x) return fail(SR3D_ERR_INVALID_ARG, "y, psf and x must be non-NULL");
-  if (!(lambda > 0.f) || !isfinite(lambda)) return fail(SR3D_ERR_INVALID_ARG, "lambda must be finite and > 0");
-  if (x == y || x == psf || (xbar && x == xbar)) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
   TikWs L;
   const size_t need = tik_layout(g, nullptr, &L);
   if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
   tik_layout(g, reinterpret_cast<char *>(ws), &L);
-  SR3D_TRY(ensure_device_tables(), "twiddle tables");
-  SR3D_TRY(pad_psf(psf, psf_dims.s, psf_dims.n, psf_dims.m, L.real, g.S, g.N, g.M, st), "pad psf");
-  SR3D_TRY(fft3d_forward(L.real, L.lam, g.S, g.N, g.M, nullptr, st), "fft Lambda");
-  SR3D_TRY(fft3d_forward(y, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st), "fft y");
-  if (xbar) SR3D_TRY(fft3d_forward(xbar, L.w, g.S, g.N, g.M, nullptr, st), "fft xbar");
-  FoldArgs fa = make_fold(g);
-  fa.W = xbar ? L.w : nullptr; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
-  fa.cw = 2.0f * lambda; fa.coefA = 2.0f * lambda; fa.tv = 0;
-  fa.partial = nullptr; fa.ctrl = nullptr; fa.done = nullptr;
-  SR3D_TRY(fold_solve(fa, false, st), "fold solve");
-  SR3D_TRY(fft3d_inverse(L.w2, x, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
-  return SR3D_OK;
+  return tikhonov_run(g, L, y, psf, psf_dims, xbar, lambda, x, st);
+}
+
+int sr3d_tikhonov_noalloc(sr3d_dims hr, sr3d_rate rate, const float *y, const float *psf,
+                          sr3d_dims psf_dims, const float *xbar, float lambda, float *x,
+                          hipStream_t st) {
+  Geometry g;
+  int rc = check_tikhonov(hr, rate, y, psf, psf_dims, xbar, lambda, x, &g);
+  if (rc) return rc;
+  TikWs L;
+  if (tik_layout(g, nullptr, &L) > sizeof(scratch))
+    return fail(SR3D_ERR_WORKSPACE, "problem needs more than the " +
+                                        std::to_string(sizeof(scratch) >> 20) +
+                                        " MiB static scratch of sr3d_tikhonov_noalloc");
+  char *base = nullptr;
+  SR3D_TRY(scratch_address(&base), "static scratch address");
+  tik_layout(g, base, &L);
+  return tikhonov_run(g, L, y, psf, psf_dims, xbar, lambda, x, st);
 }
 
 int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t ws_bytes,

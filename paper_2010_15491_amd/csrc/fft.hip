@@ -36,24 +36,47 @@ bool fft_len_supported(int n) {
 
 namespace {
 constexpr int kMaxDev = 64;
+
+// Total entries of all tables: sum of the supported lengths (and length 1).
+constexpr int tw_total() {
+  int t = 1;
+#define SR3D_SUM(L) t += L;
+  SR3D_FFT_LENGTHS(SR3D_SUM)
+#undef SR3D_SUM
+  return t;
+}
+constexpr int kTwTotal = tw_total();
+
 std::mutex g_mu;
 float2 *g_tw[kMaxDev] = {nullptr};
 int g_tw_off[kMaxLen + 1];
 bool g_off_ready = false;
-size_t g_tw_total = 0;
+float2 g_tw_host[kTwTotal];
 
 void build_offsets() {
   if (g_off_ready) return;
-  size_t off = 0;
+  int off = 0;
   for (int n = 0; n <= kMaxLen; ++n) g_tw_off[n] = -1;
-#define SR3D_OFF(L) g_tw_off[L] = (int)off; off += L;
+#define SR3D_OFF(L) g_tw_off[L] = off; off += L;
   SR3D_OFF(1)
   SR3D_FFT_LENGTHS(SR3D_OFF)
 #undef SR3D_OFF
-  g_tw_total = off;
+  for (int n = 1; n <= kMaxLen; ++n) {
+    if (g_tw_off[n] < 0) continue;
+    for (int k = 0; k < n; ++k) {
+      const double a = -2.0 * M_PI * (double)k / (double)n;
+      g_tw_host[g_tw_off[n] + k] = make_float2((float)cos(a), (float)sin(a));
+    }
+  }
   g_off_ready = true;
 }
 }  // namespace
+
+// The tables live in a static device array (28 KB), so no call of the
+// library allocates device memory for them. Every device holds its own copy;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// (the array's name in host code is a host-side stand-in, not that address).
+static __device__ __align__(256) float2 tw_table[kTwTotal];
 
 hipError_t ensure_device_tables() {
   int dev = 0;
@@ -63,23 +86,12 @@ hipError_t ensure_device_tables() {
   std::lock_guard<std::mutex> lk(g_mu);
   build_offsets();
   if (g_tw[dev]) return hipSuccess;
-  std::vector<float2> h(g_tw_total);
-  for (int n = 1; n <= kMaxLen; ++n) {
-    if (g_tw_off[n] < 0) continue;
-    for (int k = 0; k < n; ++k) {
-      const double a = -2.0 * M_PI * (double)k / (double)n;
-      h[g_tw_off[n] + k] = make_float2((float)cos(a), (float)sin(a));
-    }
-  }
-  float2 *d = nullptr;
-  e = hipMalloc(&d, g_tw_total * sizeof(float2));
+  void *d = nullptr;
+  e = hipGetSymbolAddress(&d, HIP_SYMBOL(tw_table));
   if (e != hipSuccess) return e;
-  e = hipMemcpy(d, h.data(), g_tw_total * sizeof(float2), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return e;
-  }
-  g_tw[dev] = d;
+  e = hipMemcpy(d, g_tw_host, sizeof(g_tw_host), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  g_tw[dev] = reinterpret_cast<float2 *>(d);
   return hipSuccess;
 }
 
@@ -91,16 +103,10 @@ const float2 *twiddles(int n) {
 }
 
 void release_device_tables() {
+  // The tables are static device memory, held until the process ends; this
+  // only forgets the addresses, so the next call uploads them again.
   std::lock_guard<std::mutex> lk(g_mu);
-  int cur = 0;
-  (void)hipGetDevice(&cur);
-  for (int d = 0; d < kMaxDev; ++d) {
-    if (!g_tw[d]) continue;
-    (void)hipSetDevice(d);
-    (void)hipFree(g_tw[d]);
-    g_tw[d] = nullptr;
-  }
-  (void)hipSetDevice(cur);
+  for (int d = 0; d < kMaxDev; ++d) g_tw[d] = nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -43,7 +43,7 @@ def CHECK_INTERVAL(k):
 
 OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
 
-EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tv_admm", "sr3d_batch",
+EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tikhonov_noalloc", "sr3d_tv_admm", "sr3d_batch",
            "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_cnn_param_count",
            "sr3d_cnn_init", "sr3d_cnn_workspace_size", "sr3d_cnn_forward", "sr3d_cnn_grad",
            "sr3d_cnn_adam", "sr3d_conv3d_workspace_size", "sr3d_conv3d_forward",
@@ -95,6 +95,8 @@ def load():
         lib.sr3d_workspace_size.restype = sz
         lib.sr3d_tikhonov.argtypes = [Dims, Rate, vp, vp, Dims, vp, cf, vp, vp, sz, vp]
         lib.sr3d_tikhonov.restype = ci
+        lib.sr3d_tikhonov_noalloc.argtypes = [Dims, Rate, vp, vp, Dims, vp, cf, vp, vp]
+        lib.sr3d_tikhonov_noalloc.restype = ci
         lib.sr3d_tv_admm.argtypes = [ctypes.POINTER(Problem), ci, ctypes.POINTER(Stats), vp, sz, vp]
         lib.sr3d_tv_admm.restype = ci
         lib.sr3d_batch.argtypes = [ctypes.POINTER(Problem), ci, ci, ctypes.POINTER(Stats), vp, sz, vp]
@@ -225,6 +227,25 @@ def tikhonov(y, psf, rate, lam, xbar=None, out=None, stream=None):
     _check(load().sr3d_tikhonov(dims_of(hr), rate_of(rate), _ptr(y), _ptr(psf), dims_of(psf.shape),
                                 _ptr(xbar), float(lam), _ptr(x), _ptr(ws), ws.numel(),
                                 _stream(stream)))
+    return x
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def tikhonov_noalloc(y, psf, rate, lam, xbar=None, out=None, stream=None):
+    """eq. (12) through sr3d_tikhonov_noalloc: the library's static device
+    scratch instead of a workspace (calls on one GPU must not overlap)."""
+    import torch
+    _dev_f32(y, "y")
+    _dev_f32(psf, "psf")
+    if xbar is not None:
+        _dev_f32(xbar, "xbar")
+    hr = hr_shape(tuple(y.shape), rate)
+    x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=y.device)
+    _check(load().sr3d_tikhonov_noalloc(dims_of(hr), rate_of(rate), _ptr(y), _ptr(psf),
+                                        dims_of(psf.shape), _ptr(xbar), float(lam), _ptr(x),
+                                        _stream(stream)))
     return x
 
 

@@ -156,3 +156,26 @@ def test_wavelet_host_argument_errors():
                             None) == -1
     arr = (sr3d.Problem * 1)(_prob())
     assert lib.sr3d_batch(arr, 1, sr3d.REG_HAAR, None, None, 0, None) == -1
+
+
+def test_tikhonov_noalloc_host_errors():
+    """Beyond its static scratch, or with bad arguments, the allocation-free
+    entry point fails on the host before any HIP call."""
+    lib = sr3d.load()
+    big = sr3d.Dims(256, 256, 256)
+    rc = lib.sr3d_tikhonov_noalloc(big, sr3d.Rate(2, 2, 2), 1, 9, sr3d.Dims(7, 7, 7), None,
+                                   1e-3, 17, None)
+    assert sr3d.STATUS[rc] == "SR3D_ERR_WORKSPACE"
+    assert "static scratch" in lib.sr3d_last_error().decode()
+    small = sr3d.Dims(32, 32, 32)
+    rc = lib.sr3d_tikhonov_noalloc(small, sr3d.Rate(2, 2, 2), None, 9, sr3d.Dims(5, 5, 5), None,
+                                   1e-3, 17, None)
+    assert sr3d.STATUS[rc] == "SR3D_ERR_INVALID_ARG"
+    rc = lib.sr3d_tikhonov_noalloc(small, sr3d.Rate(2, 2, 2), 1, 9, sr3d.Dims(5, 5, 5), None,
+                                   0.0, 17, None)
+    assert sr3d.STATUS[rc] == "SR3D_ERR_INVALID_ARG"
+    # the limit: a 128^3 solve fits the 64 MiB array, 256 x 128 x 128 does not
+    p = _prob(hr=(128, 128, 128), psf=(7, 7, 7))
+    assert lib.sr3d_workspace_size(sr3d.OP_TIKHONOV, ctypes.byref(p), 1) <= sr3d.NOALLOC_SCRATCH_BYTES
+    p = _prob(hr=(256, 128, 128), psf=(7, 7, 7))
+    assert lib.sr3d_workspace_size(sr3d.OP_TIKHONOV, ctypes.byref(p), 1) > sr3d.NOALLOC_SCRATCH_BYTES
