@@ -116,27 +116,58 @@ def make_inputs(torch, sr3d, phantom, wl, dev):
     return y.contiguous(), psf, x_true
 
 
-def cpu_baseline(y_np, psf_np, wl, iters_gpu, budget_s=30.0):
-    """FP64 oracle on this host: times 1 and 3 iterations of Algorithm 1 on the
-    same inputs and extrapolates setup + iters_gpu iterations."""
+def host_cpu_model():
+    """The host CPU's model name (first `model name` line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(y_np, psf_np, wl, iters_gpu, iters_timed=10):
+    """FP64 oracle on this host, on the same inputs: Algorithm 1 with 1 and
+    1 + iters_timed iterations (all of this process's cores for the FFTs),
+    giving seconds per iteration and the setup; the rate is setup + the GPU
+    run's iteration count. The same with one FFT worker, 1 and 3 iterations,
+    gives the single-thread figure."""
     import oracle as O
-    t0 = time.perf_counter()
-    O.admm_tv(y_np, psf_np, wl["rate"], wl["lam"], wl["mu"], 1)
-    t1 = time.perf_counter() - t0
-    k = 3 if t1 * 3 < budget_s else 2
-    t0 = time.perf_counter()
-    O.admm_tv(y_np, psf_np, wl["rate"], wl["lam"], wl["mu"], k)
-    tk = time.perf_counter() - t0
-    per_iter = max((tk - t1) / (k - 1), 1e-9)
-    setup = max(t1 - per_iter, 0.0)
-    total = setup + iters_gpu * per_iter
+
+    def per_iter(k):
+        t0 = time.perf_counter()
+        O.admm_tv(y_np, psf_np, wl["rate"], wl["lam"], wl["mu"], 1)
+        t1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.admm_tv(y_np, psf_np, wl["rate"], wl["lam"], wl["mu"], 1 + k)
+        tk = time.perf_counter() - t0
+        it = max((tk - t1) / k, 1e-9)
+        return it, max(t1 - it, 0.0), t1, tk
+
+    cores = int(O.WORKERS)
+    it_all, setup_all, t1, tk = per_iter(iters_timed)
+    saved = O.WORKERS
+    try:
+        O.WORKERS = 1
+        it_one, setup_one, t1s, tks = per_iter(2)
+    finally:
+        O.WORKERS = saved
     nh = wl["hr"][0] * wl["hr"][1] * wl["hr"][2]
-    return {"value": nh / total, "unit": "HR voxels/s", "cores": int(O.WORKERS),
-            "kind": "oracle",
-            "sample": (f"FP64 oracle admm_tv on the same 256^3 inputs, 1 and {k} iterations timed "
-                       f"({t1:.1f} s, {tk:.1f} s); setup {setup:.2f} s + {iters_gpu} x "
-                       f"{per_iter:.2f} s/iteration extrapolated to the GPU run's iteration count"),
-            "seconds_per_iteration": per_iter, "setup_seconds": setup}
+    total = setup_all + iters_gpu * it_all
+    return {"value": nh / total, "unit": "HR voxels/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle admm_tv on the same 256^3 inputs with {cores} FFT threads: "
+                       f"1 and {1 + iters_timed} iterations timed ({t1:.1f} s, {tk:.1f} s); "
+                       f"setup {setup_all:.2f} s + {iters_gpu} x {it_all:.2f} s/iteration, "
+                       "scaled to the GPU run's iteration count"),
+            "seconds_per_iteration": it_all, "setup_seconds": setup_all,
+            "iterations_timed": 1 + iters_timed,
+            "single_thread": {"seconds_per_iteration": it_one, "setup_seconds": setup_one,
+                              "value": nh / (setup_one + iters_gpu * it_one),
+                              "sample": f"1 and 3 iterations with 1 FFT thread ({t1s:.1f} s, "
+                                        f"{tks:.1f} s)"},
+            "host_nproc": os.cpu_count(), "host_cpu_model": host_cpu_model()}
 
 
 def main():

@@ -8,6 +8,7 @@ forward). Inputs are seeded synthetic ellipsoid phantoms.
 from __future__ import annotations
 
 import time
+from dataclasses import dataclass
 
 from . import phantom, sr3d
 
@@ -73,6 +74,34 @@ def warm_start(params, y, psf, rate, tau=1e-3, ws=None):
     """x0 = x_tik + f(x_tik) with x_tik the Tikhonov solution (eq. (12))."""
     xt = sr3d.tikhonov(y, psf, rate, tau)
     return sr3d.cnn_forward(params, xt, ws=ws)
+
+
+@dataclass
+class WarmSolve:
+    """Outcome of solve(): which start produced x, and the stats of each run."""
+    used: str                      # "warm" (accepted) or "plain" (fallback)
+    warm: sr3d.AdmmStats           # the run from the learned x0
+    plain: sr3d.AdmmStats | None   # the fallback run from x0 = 0, if it ran
+
+
+def solve(params, y, psf, rate, lam, mu, max_iter, tol, tol_dual=0.0, tau=1e-3, out=None,
+          workspace=None, cnn_ws=None, flags=sr3d.FP64_REDUCE):
+    """Algorithm 1 from the learned start, with plain ADMM as the fallback.
+
+    x0 = x_tik + f(x_tik) starts a TV-ADMM solve to `tol` (cap `max_iter`).
+    The result is accepted only if that solve meets the tolerance (both
+    relative residuals); otherwise plain ADMM from x0 = 0 runs to the same
+    tolerance and cap and its x is returned, so a caller always gets what the
+    method without the network gives unless the warm start has converged.
+    Both runs' time is paid. Returns (x, WarmSolve)."""
+    x0 = warm_start(params, y, psf, rate, tau, ws=cnn_ws)
+    x, stw = sr3d.tv_admm(y, psf, rate, lam, mu, max_iter, tol=tol, tol_dual=tol_dual, x0=x0,
+                          flags=flags, out=out, workspace=workspace)
+    if stw.converged:
+        return x, WarmSolve("warm", stw, None)
+    x, stp = sr3d.tv_admm(y, psf, rate, lam, mu, max_iter, tol=tol, tol_dual=tol_dual,
+                          flags=flags, out=x, workspace=workspace)
+    return x, WarmSolve("plain", stw, stp)
 
 
 def timed(fn):

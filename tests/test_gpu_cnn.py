@@ -187,3 +187,26 @@ def test_training_lowers_loss_and_the_warm_start_gains():
     e_cnn = float(torch.linalg.vector_norm(x0 - xa))
     print(f"held-out distance to the ADMM solution: Tikhonov {e_tik:.4f}, CNN {e_cnn:.4f}")
     assert e_cnn < 0.8 * e_tik
+
+
+def test_warm_solve_accepts_or_falls_back_to_plain_admm():
+    """warmstart.solve: the learned start is kept only when its ADMM run meets
+    the tolerance; otherwise plain ADMM (x0 = 0) runs and its x is returned,
+    bit-equal to a plain solve with the same tolerance and cap."""
+    from paper_2010_15491_amd import warmstart
+    shape, rate, lam, mu = (32, 32, 32), (2, 2, 2), 2e-3, 5e-2
+    pr = phantom.make_problem(shape, rate, 1.5, 0.02, 1010)
+    P = dev32(pr["psf"])
+    Y = sr3d.degrade(dev32(pr["x_true"]), P, rate) + dev32(pr["noise"])
+    params = sr3d.cnn_init(3)
+    # accept: a loose tolerance that the warm-started run meets
+    x, info = warmstart.solve(params, Y, P, rate, lam, mu, 200, tol=2e-2)
+    assert info.used == "warm" and info.warm.converged and info.plain is None
+    x0 = warmstart.warm_start(params, Y, P, rate)
+    xw, stw = sr3d.tv_admm(Y, P, rate, lam, mu, 200, tol=2e-2, x0=x0)
+    assert torch.equal(x, xw) and stw.iters == info.warm.iters
+    # fall back: a tolerance no run reaches within 5 iterations
+    x, info = warmstart.solve(params, Y, P, rate, lam, mu, 5, tol=1e-9)
+    assert info.used == "plain" and not info.warm.converged and info.warm.iters == 5
+    xp, stp = sr3d.tv_admm(Y, P, rate, lam, mu, 5, tol=1e-9)
+    assert torch.equal(x, xp) and info.plain.iters == stp.iters == 5
