@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--haar", type=int, default=0, metavar="LEVELS",
                     help="tv256: l1 of orthonormal Haar details with LEVELS levels "
                          "(SR3D_REG_HAAR) instead of TV")
+    ap.add_argument("--data-l1", type=float, default=0.0, metavar="MU_DATA",
+                    help="tv256: l1 data term (SR3D_DATA_L1) with this data-split penalty, on the "
+                         "same volume with impulses (+-1 on 10%% of the LR voxels) added to y")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a dispatch "
                          "of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -217,6 +220,9 @@ def main():
     dev = torch.device("cuda:0")
     wl = WORKLOAD
     y, psf, _ = make_inputs(torch, sr3d, phantom, wl, dev)
+    if args.data_l1 > 0:
+        y += torch.from_numpy(phantom.impulse_noise(tuple(y.shape), wl["seed"] + 500, 0.1, 1.0)
+                              .astype("float32")).to(dev)
     hr = wl["hr"]
     nh = hr[0] * hr[1] * hr[2]
     x = torch.empty(hr, dtype=torch.float32, device=dev)
@@ -225,7 +231,8 @@ def main():
     ws = torch.empty(sr3d.workspace_bytes(sr3d.OP_TV_ADMM, [p]), dtype=torch.uint8, device=dev)
     base_flags = (sr3d.FP64_REDUCE | (sr3d.SEPARATE_R2C if args.separate_r2c else 0)
                   | (sr3d.TV_ANISO if args.aniso else 0)
-                  | (sr3d.REG_HAAR | sr3d.HAAR_LEVELS(args.haar) if args.haar else 0))
+                  | (sr3d.REG_HAAR | sr3d.HAAR_LEVELS(args.haar) if args.haar else 0)
+                  | (sr3d.DATA_L1 if args.data_l1 > 0 else 0))
     flags = base_flags | (0 if args.no_profile else sr3d.PROFILE)
     flags_all = flags
     # FFT tile variants: timed once on this device, outside the timed steps.
@@ -238,7 +245,8 @@ def main():
 
     def step(fl=None):
         return sr3d.tv_admm(y, psf, wl["rate"], wl["lam"], wl["mu"], wl["max_iter"],
-                            tol=wl["tol"], flags=flags if fl is None else fl, out=x, workspace=ws)
+                            tol=wl["tol"], flags=flags if fl is None else fl, out=x, workspace=ws,
+                            mu_data=args.data_l1)
 
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
@@ -308,9 +316,12 @@ def main():
                    "max_iter": wl["max_iter"], "iters": stats.iters,
                    "converged": stats.converged, "primal_rel": stats.primal_rel,
                    "dual_rel": stats.dual_rel, "reductions": "fp64",
-                   "stencil": "tiled + separate R2C" if args.separate_r2c else "fused R2C",
+                   "stencil": ("tiled + separate R2C" if args.separate_r2c or args.data_l1 > 0
+                               else "fused R2C"),
                    "regulariser": (f"l1 of {args.haar}-level Haar details" if args.haar
                                    else "anisotropic TV" if args.aniso else "isotropic TV"),
+                   "data_term": (f"l1 (mu_data {args.data_l1}, impulses on 10% of y)"
+                                 if args.data_l1 > 0 else "l2"),
                    "fft_tiles_kind_len_variant": fft_tiles,
                    "parallelism": "single_gpu"},
         "roofline": roofline,

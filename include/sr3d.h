@@ -79,6 +79,7 @@ typedef struct {
   float *x;            /* device HR output [s_h][n_h][m_h] */
   float *state;        /* optional device buffer of 3*N_h floats, or NULL (see below) */
   float tol_dual;      /* tolerance of the relative dual residual; <= 0 means tol */
+  float mu_data;       /* SR3D_DATA_L1 only: ADMM penalty of the data split, > 0 */
 } sr3d_problem;
 
 /* sr3d_problem.state: the ADMM state (u, d) is kept as nu = L x + d_prev
@@ -123,6 +124,21 @@ typedef struct {
                                   Every HR dimension must be a multiple of 2^levels. Not with
                                   SR3D_TV_ANISO, SR3D_WARM_DUAL or sr3d_batch. */
 #define SR3D_HAAR_LEVELS(j) (((j) & 0xf) << 16)  /* Haar levels for SR3D_REG_HAAR, 1..8 (0: 1) */
+#define SR3D_DATA_L1     0x200000 /* l1 data term for non-Gaussian (impulsive, heavy-tailed)
+                                  noise, which the paper's conclusion (Sec. V) names as future
+                                  work: min ||D H x - y||_1 + lambda TV(x), by ADMM with a second
+                                  split v = D H x - y (penalty problem.mu_data, scaled dual e).
+                                  Step 5a is the x-step of Algorithm 1 with y -> y + v - e and
+                                  mu -> mu / mu_data (unfused x-update); steps 5b/5c are
+                                  unchanged (threshold lambda / mu); then
+                                  v' = soft(D H x - y + e, 1 / mu_data), e' = e + D H x - y - v'.
+                                  Initialisation applies both steps 5b/5c to x0 with zero duals.
+                                  Stops when both splits' relative residuals meet the tolerances:
+                                  the data split's primal |DHx - v' - y| / max(|DHx|, |v'|, |y|)
+                                  and dual |H^T D^T (v' - v)| / |H^T D^T e'|; stats report the
+                                  larger of the two splits' primal and dual, and the objective
+                                  |DHx - y|_1 + lambda TV(x). Not with SR3D_REG_HAAR,
+                                  SR3D_WARM_DUAL, SR3D_RESUME or sr3d_batch. */
 #define SR3D_CHECK_INTERVAL(k) (((k) & 0xff) << 8)  /* host polls the device stop flag every k iterations (default 8) */
 
 /* operations for sr3d_workspace_size */

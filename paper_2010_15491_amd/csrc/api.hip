@@ -34,7 +34,7 @@ long g_prof_n[kStCount] = {0};
 unsigned g_prof_mask = ~0u;  // stages timed under SR3D_PROFILE
 const char *kStageNames[kStCount] = {"fft_r2c_m", "fft_c2c_n", "fft_c2c_s", "fold_solve",
                                      "ifft_c2c_s", "ifft_c2c_n", "ifft_c2r_m", "admm_stencil",
-                                     "reduce_test", "solve_s", "stencil_r2c", "wavelet", "setup"};
+                                     "reduce_test", "solve_s", "stencil_r2c", "wavelet", "setup", "l1_data"};
 }  // namespace
 
 void prof_begin(int stage, hipStream_t st) {
@@ -200,6 +200,13 @@ struct TvWs {
   bool haar;   // l1 of Haar details (SR3D_REG_HAAR): Tikhonov fold + wavelet kernels
   int levels;  // Haar levels
   int nbSwav;  // workgroups of the wavelet ADMM kernel
+  // l1 data term (SR3D_DATA_L1): LR state v, e; DHx, y', dv = v' - v; the LR
+  // spectra of DHx, dv and e'; the weights of ||H^T D^T .||; partial sums
+  bool l1;
+  float *l1v, *l1e, *l1t, *l1yp, *l1dv, *l1w;
+  float2 *l1sa, *l1sb, *l1sc;
+  void *partL, *partW;
+  int nbL;
 };
 
 // Haar levels of SR3D_REG_HAAR (bits 16-19 of the flags; 0 means 1).
@@ -252,6 +259,20 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
     L->tab = c.take<int>(g.sp.tab.size());
     L->sdesc = c.take<SolveSArgs>(1);
   }
+  // l1 data term: LR-sized, about 5 B per HR voxel at d = 8
+  L->l1 = false;
+  L->nbL = l1_blocks(g.NL);
+  L->l1v = c.take<float>(g.NL);
+  L->l1e = c.take<float>(g.NL);
+  L->l1t = c.take<float>(g.NL);
+  L->l1yp = c.take<float>(g.NL);
+  L->l1dv = c.take<float>(g.NL);
+  L->l1w = c.take<float>(g.nlspec);
+  L->l1sa = c.take<float2>(g.nlspec);
+  L->l1sb = c.take<float2>(g.nlspec);
+  L->l1sc = c.take<float2>(g.nlspec);
+  L->partL = c.take<double>((size_t)5 * L->nbL);
+  L->partW = c.take<double>((size_t)2 * l1_blocks(g.nlspec));
   return c.off + 256;
 }
 
@@ -262,6 +283,14 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->aniso = (flags & SR3D_TV_ANISO) != 0;
   L->haar = (flags & SR3D_REG_HAAR) != 0;
   L->levels = haar_levels(flags);
+  L->l1 = (flags & SR3D_DATA_L1) != 0;
+  if (L->l1) {
+    // The l1 data term runs the x-update on the natural spectrum (the fold
+    // kernel gives the LR spectrum of D H x) and the tiled stencil.
+    L->fused = false;
+    L->nbF = L->nbFold;
+    L->fsten = false;
+  }
   L->nbS = L->fsten ? L->nbSrow : L->nbStile;
   if (L->haar) {
     // The x-step is the Tikhonov solve (A = mu): the fused x-update with
@@ -359,6 +388,13 @@ int check_problem(const sr3d_problem *p, int flags, Geometry *g) {
       return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR needs every HR dimension a multiple of 2^levels");
     if (flags & (SR3D_TV_ANISO | SR3D_WARM_DUAL))
       return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR excludes SR3D_TV_ANISO and SR3D_WARM_DUAL");
+  }
+  if (flags & SR3D_DATA_L1) {
+    if (!(p->mu_data > 0.f) || !isfinite(p->mu_data))
+      return fail(SR3D_ERR_INVALID_ARG, "SR3D_DATA_L1 needs mu_data finite and > 0");
+    if (flags & (SR3D_REG_HAAR | SR3D_WARM_DUAL | SR3D_RESUME))
+      return fail(SR3D_ERR_INVALID_ARG,
+                  "SR3D_DATA_L1 excludes SR3D_REG_HAAR, SR3D_WARM_DUAL and SR3D_RESUME");
   }
   if (p->x == p->y || p->x == p->psf) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
   return SR3D_OK;
@@ -502,6 +538,75 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
   return reduce_and_test(L.ctrl, L.partS, L.nbS, L.partF, L.nbF, fp64, st);
 }
 
+// l1 data term, initialisation: steps 5b'/5c' applied to x0 with zero
+// duals (a = D H x0 - y, v = soft(a, 1/mu_data), e = a - v), y' = y + v - e
+// and its LR spectrum for the first x-step; the weights of ||H^T D^T .||.
+// `tmp` is an HR scratch volume (the state buffer the first iteration writes).
+hipError_t l1_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *tmp,
+                    hipStream_t st) {
+  hipError_t e;
+  if ((e = l1_weights(L.lam, L.l1w, g.S, g.N, g.M, g.dr, g.dc, g.ds, st))) return e;
+  const float *t = nullptr;  // D H x0 (x0 = 0: none)
+  if (p->x0) {
+    if ((e = fft3d_forward(p->x0, L.w2, g.S, g.N, g.M, nullptr, st))) return e;
+    if ((e = spectrum_mul(L.w2, L.lam, (size_t)g.nspec, (float)(1.0 / (double)g.NH), st))) return e;
+    if ((e = fft3d_inverse(L.w2, tmp, g.S, g.N, g.M, 1.0f, nullptr, st))) return e;
+    if ((e = decimate(tmp, L.l1t, g.S, g.N, g.M, g.dr, g.dc, g.ds, st))) return e;
+    t = L.l1t;
+  }
+  if ((e = l1_update(t, p->y, L.l1v, L.l1e, L.l1yp, nullptr, g.NL, 1.0f / p->mu_data, true, nullptr,
+                     false, nullptr, st)))
+    return e;
+  return fft3d_forward(L.l1yp, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st);
+}
+
+// One iteration with the l1 data term: the x-step of Algorithm 1 with
+// y -> y' (its LR spectrum in yh) and mu -> mu / mu_data, whose fold also
+// leaves the LR spectrum of D H x; steps 5b/5c (tiled stencil, threshold
+// lam / mu); then on the LR grid D H x, steps 5b'/5c', the spectrum of the
+// next y', the data split's dual norms, and the stopping test over both
+// splits.
+hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
+                        int k, bool fp64, hipStream_t st) {
+  const int *done = &L.ctrl->done;
+  hipError_t e;
+  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+  const float mur = p->mu / p->mu_data;
+  FoldArgs fa = make_fold(g);
+  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+  fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+  fa.cw = mur; fa.coefA = mur; fa.tv = 1;
+  fa.partial = nullptr; fa.ctrl = L.ctrl; fa.done = done; fa.dhx = L.l1sa;
+  if ((e = fold_solve(fa, fp64, st))) return e;
+  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  AdmmStencilArgs sa{};
+  sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
+  sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
+  sa.part = L.partS; sa.done = done; sa.aniso = L.aniso ? 1 : 0;
+  if ((e = admm_stencil(sa, true, fp64, st))) return e;
+  const int saved = t_prof.override_stage;
+  t_prof.override_stage = kStL1Data;
+  e = fft3d_inverse(L.l1sa, L.l1t, g.Sl, g.Nl, g.Ml, (float)(1.0 / (double)g.NL), done, st);
+  if (!e) {
+    prof_begin(kStL1Data, st);
+    e = l1_update(L.l1t, p->y, L.l1v, L.l1e, L.l1yp, L.l1dv, g.NL, 1.0f / p->mu_data, false,
+                  L.partL, fp64, done, st);
+    prof_end(st);
+  }
+  if (!e) e = fft3d_forward(L.l1yp, L.yh, g.Sl, g.Nl, g.Ml, done, st);
+  if (!e) e = fft3d_forward(L.l1dv, L.l1sb, g.Sl, g.Nl, g.Ml, done, st);
+  if (!e) e = fft3d_forward(L.l1e, L.l1sc, g.Sl, g.Nl, g.Ml, done, st);
+  if (!e) {
+    prof_begin(kStL1Data, st);
+    e = l1_wnorm(L.l1sb, L.l1sc, L.l1w, g.nlspec, L.partW, fp64, done, st);
+    prof_end(st);
+  }
+  t_prof.override_stage = saved;
+  if (e) return e;
+  return l1_reduce_test(L.ctrl, L.partS, L.nbS, L.partL, L.nbL, L.partW, l1_blocks(g.nlspec), fp64,
+                        st);
+}
+
 // Enqueue iteration k (1-based): reads nu[(k-1)%2], writes nu[k%2]. The
 // stopping test of an iteration runs in an extra workgroup of the next
 // iteration's first launch (fused path, not the first iteration of an
@@ -510,6 +615,7 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
 hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
                         int k, bool fp64, hipStream_t st, bool merged, bool last) {
   if (L.haar) return wavelet_iteration(g, L, p, nu, k, fp64, st, merged, last);
+  if (L.l1) return l1_iteration(g, L, p, nu, k, fp64, st);
   const int *done = &L.ctrl->done;
   hipError_t e;
   // The iteration's first launch can carry the previous reduction: the R2C
@@ -577,6 +683,7 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   ProfScope prof((flags & SR3D_PROFILE) && !(flags & SR3D_USE_GRAPH));
   t_prof.override_stage = prof.on ? kStSetup : -1;
   SR3D_TRY(tv_setup(g, L, p, nu[0], flags, st), "tv setup");
+  if (L.l1) SR3D_TRY(l1_setup(g, L, p, nu[1], st), "l1 data setup");
   t_prof.override_stage = -1;
   int K = check_interval(flags);
   if (flags & SR3D_USE_GRAPH) {
@@ -878,7 +985,8 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
 int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
               size_t ws_bytes, hipStream_t st) {
   if (!p || count < 1) return fail(SR3D_ERR_INVALID_ARG, "no problems");
-  if (flags & SR3D_REG_HAAR) return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR is not supported by sr3d_batch");
+  if (flags & (SR3D_REG_HAAR | SR3D_DATA_L1))
+    return fail(SR3D_ERR_INVALID_ARG, "SR3D_REG_HAAR and SR3D_DATA_L1 are not supported by sr3d_batch");
   Geometry g0;
   for (int i = 0; i < count; ++i) {
     int rc = check_problem(&p[i], flags, &g0);

@@ -175,15 +175,21 @@ __device__ __forceinline__ void fold_body(const FoldArgs &a, int bid) {
         suQ.y += lb.y * inv;
       }
     }
-    // Data residual of the new x: Y_j - (1/d) sum_a L_a X_a (LR Parseval).
-    if (a.partial) {
-      float2 acc = make_float2(0.f, 0.f);
+    // (1/d) sum_a L_a X_a is the LR spectrum of D H x at j (eq. (8)): the
+    // data residual Y_j - it (LR Parseval), and with `dhx` that spectrum at
+    // the stored LR entries.
+    float2 acc = make_float2(0.f, 0.f);
+    if (a.partial || a.dhx) {
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         const float2 lx = c_mul(lam[q], X[q]);
         acc.x += lx.x;
         acc.y += lx.y;
       }
+    }
+    if (a.dhx && jm < a.Mlh)
+      a.dhx[((long)js * a.Nl + jn) * a.Mlh + jm] = make_float2(acc.x / fd, acc.y / fd);
+    if (a.partial) {
       const Acc rr = (Acc)Yj.x - (Acc)acc.x / (Acc)D;
       const Acc ri = (Acc)Yj.y - (Acc)acc.y / (Acc)D;
       // weight 2 for groups whose conjugate partner is not processed (dr = 1)

@@ -52,7 +52,7 @@ struct FastDiv {
 // launch on its stream when the calling thread has profiling switched on.
 enum Stage {
   kStFftR2cM, kStFftN, kStFftS, kStFold, kStIfftS, kStIfftN, kStIfftC2rM,
-  kStStencil, kStReduce, kStSolveS, kStStencilR2c, kStWavelet, kStSetup, kStCount
+  kStStencil, kStReduce, kStSolveS, kStStencilR2c, kStWavelet, kStSetup, kStL1Data, kStCount
 };
 void prof_begin(int stage, hipStream_t st);
 void prof_end(hipStream_t st);
@@ -180,6 +180,7 @@ struct FoldArgs {
   void *partial;      // data-term partial sums, one per workgroup (Acc), or null
   Ctrl *ctrl;
   const int *done;
+  float2 *dhx;        // LR half spectrum of D H x for the new x (unscaled), or null
 };
 int fold_blocks(const FoldArgs &a);
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
@@ -292,6 +293,18 @@ struct ReduceDesc {
 };
 hipError_t reduce_and_test_batch(const ReduceDesc *descs, int nvol, int *active, bool fp64,
                                  hipStream_t st);
+
+// l1 data term (l1data.hip): LR-grid steps of the second split v = D H x - y.
+hipError_t l1_weights(const float2 *lam, float *w, int S, int N, int M, int dr, int dc, int ds,
+                      hipStream_t st);
+int l1_blocks(long n);
+hipError_t l1_update(const float *t, const float *y, float *v, float *e, float *yp, float *dv,
+                     long n, float thr, bool init, void *part, bool fp64, const int *done,
+                     hipStream_t st);
+hipError_t l1_wnorm(const float2 *A, const float2 *B, const float *w, long n, void *part, bool fp64,
+                    const int *done, hipStream_t st);
+hipError_t l1_reduce_test(Ctrl *c, const void *ps, int nbs, const void *pl, int nbl, const void *pw,
+                          int nbw, bool fp64, hipStream_t st);
 
 // Setup kernels.
 hipError_t pad_psf(const float *psf, int Ks, int Kn, int Km, float *out, int S, int N, int M,

@@ -21,6 +21,10 @@ Recipe (the paper's tooth scans are not available; these phantoms stand in):
   * noise: sigma_n * N(0,1) on the LR grid, drawn after phantom and texture.
   * PSF: separable sampled Gaussian exp(-i^2 / (2 sigma^2)) at integer offsets
     i in [-K//2, K//2], K = 2*ceil(2 sigma) + 1 per axis, normalised to sum 1.
+  * impulse noise (the non-Gaussian noise an l1 data term is for):
+    ``default_rng(seed)``; each LR voxel is hit with probability ``frac``
+    (uniform draw < frac), then gets +amp or -amp with equal probability;
+    added to the Gaussian noise above.
 """
 
 from __future__ import annotations
@@ -30,7 +34,7 @@ import math
 import numpy as np
 
 __all__ = ["psf_size", "gaussian_psf", "ellipsoid_phantom", "texture_field",
-           "make_problem", "lr_shape"]
+           "make_problem", "lr_shape", "impulse_noise"]
 
 
 def psf_size(sigma):
@@ -121,3 +125,11 @@ def make_problem(hr_shape, rate, sigma, noise_sigma, seed, texture=False,
     noise = noise_sigma * rng.standard_normal(lr_shape(hr_shape, rate))
     return {"x_true": x, "psf": gaussian_psf(sigma), "noise": noise,
             "rate": tuple(rate)}
+
+
+def impulse_noise(shape, seed, frac=0.1, amp=1.0):
+    """Sparse +-amp impulses on a fraction ``frac`` of the voxels of ``shape``."""
+    rng = np.random.default_rng(seed)
+    hit = rng.random(shape) < frac
+    sign = np.where(rng.random(shape) < 0.5, -1.0, 1.0)
+    return hit * sign * float(amp)

@@ -30,6 +30,7 @@ UNFUSED = 0x20
 SEPARATE_R2C = 0x40
 TV_ANISO = 0x80
 REG_HAAR = 0x100000
+DATA_L1 = 0x200000
 
 
 def HAAR_LEVELS(j):
@@ -71,7 +72,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("hr", Dims), ("rate", Rate), ("y", ctypes.c_void_p), ("psf", ctypes.c_void_p),
                 ("psf_dims", Dims), ("lambda_tv", ctypes.c_float), ("mu", ctypes.c_float),
                 ("tol", ctypes.c_float), ("max_iter", ctypes.c_int), ("x0", ctypes.c_void_p),
-                ("x", ctypes.c_void_p), ("state", ctypes.c_void_p), ("tol_dual", ctypes.c_float)]
+                ("x", ctypes.c_void_p), ("state", ctypes.c_void_p), ("tol_dual", ctypes.c_float),
+                ("mu_data", ctypes.c_float)]
 
 
 class Sr3dError(RuntimeError):
@@ -195,10 +197,10 @@ def _workspace(nbytes, device):
 
 
 def _problem(hr_shape, rate, psf, lam=1.0, mu=1.0, tol=0.0, max_iter=1, y=None, x=None, x0=None,
-             state=None, tol_dual=0.0):
+             state=None, tol_dual=0.0, mu_data=0.0):
     return Problem(dims_of(hr_shape), rate_of(rate), _ptr(y), _ptr(psf), dims_of(psf.shape),
                    float(lam), float(mu), float(tol), int(max_iter), _ptr(x0), _ptr(x), _ptr(state),
-                   float(tol_dual))
+                   float(tol_dual), float(mu_data))
 
 
 def lr_shape(hr_shape, rate):
@@ -264,8 +266,10 @@ def _stats(s):
 
 
 def tv_admm(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE, state=None,
-            out=None, workspace=None, stream=None, tol_dual=0.0):
-    """3D-FSR-l2-TV (Algorithm 1). Returns (x, AdmmStats)."""
+            out=None, workspace=None, stream=None, tol_dual=0.0, mu_data=0.0):
+    """3D-FSR-l2-TV (Algorithm 1). Returns (x, AdmmStats). With DATA_L1 in
+    ``flags`` the data term is ||DHx - y||_1 and ``mu_data`` the penalty of
+    its split."""
     import torch
     _dev_f32(y, "y")
     _dev_f32(psf, "psf")
@@ -276,7 +280,7 @@ def tv_admm(y, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE
     hr = hr_shape(tuple(y.shape), rate)
     x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=y.device)
     p = _problem(hr, rate, psf, lam, mu, tol, max_iter, y=y, x=x, x0=x0, state=state,
-                 tol_dual=tol_dual)
+                 tol_dual=tol_dual, mu_data=mu_data)
     need = workspace_bytes(OP_TV_ADMM, [p])
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, y.device)
     st = Stats()

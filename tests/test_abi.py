@@ -113,7 +113,7 @@ def _header_flags():
 def test_binding_flag_values_match_the_header():
     flags = _header_flags()
     for name in ("FP64_REDUCE", "RESUME", "USE_GRAPH", "PROFILE", "WARM_DUAL", "UNFUSED",
-                 "SEPARATE_R2C", "TV_ANISO", "REG_HAAR"):
+                 "SEPARATE_R2C", "TV_ANISO", "REG_HAAR", "DATA_L1"):
         assert getattr(sr3d, name) == flags[name], name
     # single bits, none inside the CHECK_INTERVAL (8-15) or HAAR_LEVELS (16-19) fields
     bits = [flags[n] for n in flags if n not in ("ERR_INVALID_ARG",)]
@@ -132,7 +132,7 @@ def test_header_compiles_as_c():
         pytest.skip("needs gcc and the ROCm headers")
     src = ('#include "sr3d.h"\n'
            "int f(void) { return SR3D_CHECK_INTERVAL(3) | SR3D_HAAR_LEVELS(2) | SR3D_REG_HAAR"
-           " | SR3D_TV_ANISO | SR3D_SEPARATE_R2C; }\n")
+           " | SR3D_TV_ANISO | SR3D_SEPARATE_R2C | SR3D_DATA_L1; }\n")
     with tempfile.TemporaryDirectory() as td:
         c = os.path.join(td, "h.c")
         with open(c, "w") as f:
@@ -179,3 +179,23 @@ def test_tikhonov_noalloc_host_errors():
     assert lib.sr3d_workspace_size(sr3d.OP_TIKHONOV, ctypes.byref(p), 1) <= sr3d.NOALLOC_SCRATCH_BYTES
     p = _prob(hr=(256, 128, 128), psf=(7, 7, 7))
     assert lib.sr3d_workspace_size(sr3d.OP_TIKHONOV, ctypes.byref(p), 1) > sr3d.NOALLOC_SCRATCH_BYTES
+
+
+def test_l1_data_host_argument_errors():
+    """SR3D_DATA_L1 needs mu_data > 0 and excludes the Haar form, the dual
+    warm start, resume and the batch; all rejected before any HIP call."""
+    lib = sr3d.load()
+    p = _prob()
+    p.mu_data = 0.0
+    assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.DATA_L1, None, None, 0, None) == -1
+    assert "mu_data" in lib.sr3d_last_error().decode()
+    p.mu_data = float("inf")
+    assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.DATA_L1, None, None, 0, None) == -1
+    p.mu_data = 1.0
+    for extra in (sr3d.REG_HAAR, sr3d.WARM_DUAL, sr3d.RESUME):
+        assert lib.sr3d_tv_admm(ctypes.byref(p), sr3d.DATA_L1 | extra, None, None, 0, None) == -1
+    # valid arguments reach the workspace check
+    assert sr3d.STATUS[lib.sr3d_tv_admm(ctypes.byref(p), sr3d.DATA_L1, None, None, 0, None)] == \
+        "SR3D_ERR_WORKSPACE"
+    arr = (sr3d.Problem * 1)(p)
+    assert lib.sr3d_batch(arr, 1, sr3d.DATA_L1, None, None, 0, None) == -1
