@@ -43,7 +43,7 @@ __all__ = [
     "grad", "grad_adjoint", "shrink", "shrink_aniso", "tikhonov", "tikhonov_objective",
     "haar3", "haar3_inverse", "haar_detail_mask", "shrink_detail", "wavelet_objective",
     "admm_wavelet", "soft", "l1data_objective", "l1data_residuals", "L1AdmmResult",
-    "admm_l1data",
+    "admm_l1data", "gaussian_taps", "separable_blur", "psf_fit_residual", "fit_gaussian_psf",
     "x_update", "AdmmResult", "stopping_residuals", "admm_tv", "min_norm_dual", "tv_objective",
     "data_term", "rel_l2",
 ]
@@ -643,6 +643,56 @@ def admm_l1data(y, psf, rate, lam, mu, mu_data, max_iter, tol=0.0, x0=None, reco
             break
     return L1AdmmResult(x=x, u=u, d=d, iters=it, converged=converged, primal_rel=prel,
                         dual_rel=drel, history=hist, v=v, e=e)
+
+
+# ---------------------------------------------------------------------------
+# PSF estimation (Sec. IV-B): the PSF of the real data is estimated by fitting
+# a 3D Gaussian; the paper reports only the fitted widths. Reading: the HR
+# reference x (the micro-CT, registered to the CBCT grid) and the LR volume y
+# are given, and sigma = (sigma_m, sigma_n, sigma_s) of a separable, sampled,
+# normalised Gaussian on a fixed support, with an intensity gain alpha and
+# offset beta, minimises 1/2 ||y - alpha D H_sigma x - beta||^2.
+# ---------------------------------------------------------------------------
+
+def gaussian_taps(sigma, radius):
+    """g[i] = exp(-i^2 / (2 sigma^2)) / sum, i = -radius..radius."""
+    i = np.arange(-int(radius), int(radius) + 1, dtype=np.float64)
+    g = np.exp(-(i * i) / (2.0 * float(sigma) ** 2))
+    return g / g.sum()
+
+
+def separable_blur(x, sigma, radius):
+    """H_sigma x in the spatial domain: circular convolution with
+    gaussian_taps along m, n and s in turn (``sigma``, ``radius`` as
+    (m, n, s)); the kernel is symmetric, so convolution = correlation."""
+    from scipy import ndimage
+    out = np.asarray(x, np.float64)
+    for axis, sg, r in ((2, sigma[0], radius[0]), (1, sigma[1], radius[1]),
+                        (0, sigma[2], radius[2])):
+        out = ndimage.correlate1d(out, gaussian_taps(sg, r), axis=axis, mode="wrap")
+    return out
+
+
+def psf_fit_residual(theta, x, y, rate, radius):
+    """y - alpha D H_sigma x - beta for theta = (sigma_m, sigma_n, sigma_s,
+    alpha, beta), flattened."""
+    sm, sn, ss, alpha, beta = (float(t) for t in theta)
+    model = decimate(separable_blur(x, (sm, sn, ss), radius), rate)
+    return (np.asarray(y, np.float64) - alpha * model - beta).ravel()
+
+
+def fit_gaussian_psf(x, y, rate, sigma0, radius, alpha0=1.0, beta0=0.0):
+    """Least-squares fit of (sigma, alpha, beta) by scipy's trust-region
+    solver (numerical Jacobian), from sigma0. Returns (sigma, alpha, beta,
+    1/2 ||residual||^2)."""
+    from scipy.optimize import least_squares
+    th0 = np.array(list(sigma0) + [alpha0, beta0], np.float64)
+    lo = np.array([0.05, 0.05, 0.05, -np.inf, -np.inf])
+    res = least_squares(psf_fit_residual, th0, args=(x, y, rate, radius), bounds=(lo, np.inf),
+                        method="trf", x_scale="jac", xtol=1e-14, ftol=1e-14, gtol=1e-14,
+                        max_nfev=500)
+    th = res.x
+    return tuple(th[:3]), float(th[3]), float(th[4]), 0.5 * float(np.sum(res.fun ** 2))
 
 
 # ---------------------------------------------------------------------------
