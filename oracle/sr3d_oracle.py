@@ -43,7 +43,8 @@ __all__ = [
     "grad", "grad_adjoint", "shrink", "shrink_aniso", "tikhonov", "tikhonov_objective",
     "haar3", "haar3_inverse", "haar_detail_mask", "shrink_detail", "wavelet_objective",
     "admm_wavelet", "soft", "l1data_objective", "l1data_residuals", "L1AdmmResult",
-    "admm_l1data", "gaussian_taps", "separable_blur", "psf_fit_residual", "fit_gaussian_psf",
+    "admm_l1data", "shift", "mf_normal_solve", "tikhonov_mf", "admm_tv_mf", "mf_data_term",
+    "gaussian_taps", "separable_blur", "psf_fit_residual", "fit_gaussian_psf",
     "x_update", "AdmmResult", "stopping_residuals", "admm_tv", "min_norm_dual", "tv_objective",
     "data_term", "rel_l2",
 ]
@@ -643,6 +644,131 @@ def admm_l1data(y, psf, rate, lam, mu, mu_data, max_iter, tol=0.0, x0=None, reco
             break
     return L1AdmmResult(x=x, u=u, d=d, iters=it, converged=converged, primal_rel=prel,
                         dual_rel=drel, history=hist, v=v, e=e)
+
+
+# ---------------------------------------------------------------------------
+# 3D multi-frame SR (Sec. V names it as future work): F LR frames
+# y_f = D S_f H x + n_f of one HR volume, S_f a known circular shift of the HR
+# grid by t_f = (t_m, t_n, t_s) voxels, (S_f z)[i] = z[i + t_f]. With
+# F(S_f z)_k = w_f(k) Z_k, w_f(k) = exp(+2 pi i k . t_f / n), eq. (8) gives
+# F_LR(y_f)_j = (1/d) sum_a w_f(k_a) Lambda_a X_a over the alias group of j,
+# so the normal equations still split into one d x d system per group, now
+# with F rank-one terms:
+#   sum_f conj(v_f) (1/d) v_f^T X + diag(A) X = B,  v_f = w_f Lambda,
+#   B_a = sum_f conj(v_f,a) F_LR(y_f)_j + c W_a.
+# ---------------------------------------------------------------------------
+
+def shift(z, t):
+    """S z with (S z)[i] = z[i + t] (circular), t = (t_m, t_n, t_s)."""
+    return np.roll(z, shift=(-int(t[2]), -int(t[1]), -int(t[0])), axis=(0, 1, 2))
+
+
+def _mf_phase(shape, t):
+    """w(k) = exp(2 pi i (k_m t_m / M + k_n t_n / N + k_s t_s / S))."""
+    S, N, M = shape
+    ps = np.exp(2j * np.pi * np.arange(S) * t[2] / S)
+    pn = np.exp(2j * np.pi * np.arange(N) * t[1] / N)
+    pm = np.exp(2j * np.pi * np.arange(M) * t[0] / M)
+    return ps[:, None, None] * pn[None, :, None] * pm[None, None, :]
+
+
+def _groups(z, rate):
+    """HR spectrum (S, N, M) -> (S_l, N_l, M_l, d) member arrays, members in
+    the order (c, b, a) of the alias offsets (c along s, b along n, a along m)."""
+    ds, dc, dr = _axes_rate(rate)
+    S, N, M = z.shape
+    v = z.reshape(ds, S // ds, dc, N // dc, dr, M // dr)
+    return v.transpose(1, 3, 5, 0, 2, 4).reshape(S // ds, N // dc, M // dr, ds * dc * dr)
+
+
+def _ungroups(g, rate, shape):
+    ds, dc, dr = _axes_rate(rate)
+    S, N, M = shape
+    v = g.reshape(S // ds, N // dc, M // dr, ds, dc, dr).transpose(3, 0, 4, 1, 5, 2)
+    return v.reshape(shape)
+
+
+def mf_normal_solve(Yf, otf, phases, A, W, c, rate):
+    """Per alias group, numpy.linalg.solve of
+    (sum_f conj(v_f) (1/d) v_f^T + diag(A)) X = B,  v_f = phase_f Lambda,
+    B = sum_f conj(v_f) Y_f[j] + c W (W may be None). Yf: list of LR spectra
+    (full, complex); returns the HR spectrum X."""
+    d = int(np.prod(rate))
+    shape = otf.shape
+    V = [_groups(ph * otf, rate) for ph in phases]          # (..., d) each
+    Ag = _groups(np.broadcast_to(A, shape).astype(complex), rate)
+    K = np.zeros(Ag.shape + (d,), complex)
+    B = np.zeros(Ag.shape, complex)
+    for v, y in zip(V, Yf):
+        K += np.conj(v)[..., :, None] * v[..., None, :] / d
+        B += np.conj(v) * y[..., None]
+    K += Ag[..., :, None] * np.eye(d)
+    if W is not None:
+        B += c * _groups(W, rate)
+    X = np.linalg.solve(K, B[..., None])[..., 0]
+    return _ungroups(X, rate, shape)
+
+
+def tikhonov_mf(ys, shifts, psf, rate, lam, xbar=None):
+    """Multi-frame eq. (5): min sum_f 1/2 ||y_f - D S_f H x||^2 + lam ||x - xbar||^2,
+    solved per alias group (A = 2 lam, c = 2 lam, W = F xbar)."""
+    ys = [np.asarray(y, np.float64) for y in ys]
+    hr = hr_shape_of(ys[0].shape, rate)
+    otf = psf_to_otf(psf, hr)
+    phases = [_mf_phase(hr, t) for t in shifts]
+    Yf = [_fftn(y) for y in ys]
+    W = None if xbar is None else _fftn(np.asarray(xbar, np.float64))
+    X = mf_normal_solve(Yf, otf, phases, np.full(hr, 2.0 * lam), W, 2.0 * lam, rate)
+    return np.real(_ifftn(X))
+
+
+def mf_data_term(x, ys, shifts, psf, rate):
+    """sum_f 1/2 ||y_f - D S_f H x||^2."""
+    otf = psf_to_otf(psf, x.shape)
+    hx = blur(x, otf)
+    return 0.5 * sum(float(np.sum((np.asarray(y) - decimate(shift(hx, t), rate)) ** 2))
+                     for y, t in zip(ys, shifts))
+
+
+def admm_tv_mf(ys, shifts, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, record=False,
+               callback=None, aniso=False):
+    """Algorithm 1 with the multi-frame data term: step 5a is the multi-frame
+    normal equations (A = mu G, c = mu, W = F Theta) solved per group;
+    steps 5b/5c and the stopping rule are unchanged."""
+    ys = [np.asarray(y, np.float64) for y in ys]
+    hr = hr_shape_of(ys[0].shape, rate)
+    otf = psf_to_otf(psf, hr)
+    G = diff_symbol_sq(hr)
+    phases = [_mf_phase(hr, t) for t in shifts]
+    Yf = [_fftn(y) for y in ys]
+    thr = lam / mu
+    prox = shrink_aniso if aniso else shrink
+    x = np.zeros(hr) if x0 is None else np.asarray(x0, np.float64).copy()
+    nu = grad(x)
+    u = prox(nu, thr)
+    d = nu - u
+    hist = []
+    it = 0
+    converged = False
+    prel = drel = float("inf")
+    for it in range(1, max_iter + 1):
+        theta = grad_adjoint(u - d)
+        X = mf_normal_solve(Yf, otf, phases, mu * G, _fftn(theta), mu, rate)
+        x = np.real(_ifftn(X))
+        Lx = grad(x)
+        u_new = prox(Lx + d, thr)
+        d_new = d + (Lx - u_new)
+        prel, drel = stopping_residuals(Lx, u, u_new, d_new, grad_adjoint, mu)
+        if record:
+            hist.append((prel, drel))
+        if callback is not None:
+            callback(it, x, u, d, u_new, d_new)
+        u, d = u_new, d_new
+        if tol > 0 and prel <= tol and drel <= tol:
+            converged = True
+            break
+    return AdmmResult(x=x, u=u, d=d, iters=it, converged=converged,
+                      primal_rel=prel, dual_rel=drel, history=hist)
 
 
 # ---------------------------------------------------------------------------
