@@ -147,6 +147,9 @@ typedef struct {
 #define SR3D_OP_BATCH    3
 #define SR3D_OP_DEGRADE  4
 #define SR3D_OP_FFT      5
+#define SR3D_OP_PSF_FIT  6
+#define SR3D_OP_TIKHONOV_MF 7  /* count = number of frames */
+#define SR3D_OP_TV_ADMM_MF  8  /* count = number of frames */
 
 /* Workspace bytes needed by `op` for problem(s) p[0..count-1] (count = 1
  * except for SR3D_OP_BATCH). Only hr, rate and psf_dims are read. Returns 0
@@ -194,12 +197,59 @@ int sr3d_tikhonov_noalloc(sr3d_dims hr, sr3d_rate rate, const float *y, const fl
 int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats,
                  void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* 3D multi-frame SR (named as future work in Sec. V): nframes (1..4) LR
+ * volumes y[f] of the same HR volume, frame f observed after a circular
+ * shift of the HR grid by shifts[3 f + (0, 1, 2)] = (t_m, t_n, t_s) voxels:
+ * y_f = D S_f H x + n_f with (S_f z)[i] = z[i + t_f]. Because a shift is a
+ * phase factor in the Fourier domain, eq. (8) still splits the normal
+ * equations into one d x d system per alias group, with one rank-one term
+ * per frame; it is solved in FP64 through an F x F Woodbury system (and the
+ * zero-frequency group of a TV solve by a Schur complement). y is a host
+ * array of device pointers, shifts a host array; d must be 1, 2, 4, 8, 16 or
+ * 32. Workspace: sr3d_workspace_size(SR3D_OP_TIKHONOV_MF or
+ * SR3D_OP_TV_ADMM_MF, p, nframes).
+ * sr3d_tikhonov_mf: min sum_f 1/2 ||y_f - D S_f H x||^2 + lambda ||x - xbar||^2.
+ * sr3d_tv_admm_mf: Algorithm 1 with the data term sum_f 1/2 ||y_f - D S_f H x||^2
+ * (problem.y is not read; the unfused x-update and the tiled stencil run);
+ * the flags of sr3d_tv_admm except SR3D_REG_HAAR, SR3D_WARM_DUAL and
+ * SR3D_DATA_L1. The objective reports the multi-frame data term. */
+int sr3d_tikhonov_mf(sr3d_dims hr, sr3d_rate rate, int nframes, const float *const *y,
+                     const int *shifts, const float *psf, sr3d_dims psf_dims, const float *xbar,
+                     float lambda, float *x, void *ws, size_t ws_bytes, hipStream_t stream);
+int sr3d_tv_admm_mf(const sr3d_problem *p, int nframes, const float *const *y, const int *shifts,
+                    int flags, sr3d_stats *stats, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Many independent TV problems p[0..count-1] of uneven sizes and rates,
  * solved together: each stage of an iteration is one launch over all active
  * volumes; converged volumes drop out on the device. stats: host array of
  * `count` entries or NULL. */
 int sr3d_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats,
                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* PSF estimation (Sec. IV-B: the PSF of the real data is a fitted 3D
+ * Gaussian). From an HR reference x (e.g. a micro-CT registered to the LR
+ * grid) and the LR volume y, fits sigma = (sigma_m, sigma_n, sigma_s) of a
+ * separable Gaussian sampled on 2 radius[a] + 1 taps per axis and normalised
+ * to sum 1, with an intensity gain and offset:
+ *   min 1/2 ||y - gain D H_sigma x - offset||^2,
+ * by Levenberg-Marquardt steps on the Gauss-Newton model; each step is one
+ * pass over the spectrum of x (eq. (8): the LR spectrum of D H_sigma x is
+ * the alias-group mean of Lambda X). The offset only moves the zero
+ * frequency and is solved exactly. Starts from sigma0 and the least-squares
+ * gain for it; stops when a step changes no parameter by more than `tol`
+ * relative (FP32 data fix the minimiser to about 1e-7 relative, so 1e-6 is
+ * a natural choice), or after max_iter steps. x HR and y LR device volumes; res
+ * (host) receives the fit; the call synchronises `stream`. */
+typedef struct {
+  double sigma[3];   /* (sigma_m, sigma_n, sigma_s) */
+  double gain, offset;
+  double objective;  /* 1/2 ||y - gain D H_sigma x - offset||^2 at the fit */
+  int passes;        /* passes over the spectrum */
+  int converged;     /* 1 if the step tolerance was met */
+} sr3d_psf_fit_result;
+int sr3d_psf_fit(sr3d_dims hr, sr3d_rate rate, const float *x, const float *y, const int radius[3],
+                 const double sigma0[3], int max_iter, double tol, sr3d_psf_fit_result *res,
+                 void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Forward model of eq. (1) without noise: y = D H x (circular blur by the
  * PSF, then decimation). x device HR, y device LR. */

@@ -23,7 +23,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsr3d.so")
 
 SOURCES = ["solve_s_i0.hip", "solve_s_i1.hip", "solve_s_i2.hip", "solve_s_i3.hip", "fft.hip",
-           "fft_m.hip", "fft_strided.hip", "fold.hip", "solve_s.hip", "stencil.hip", "stencil_r2c.hip", "haar.hip", "l1data.hip", "cnn.hip",
+           "fft_m.hip", "fft_strided.hip", "fold.hip", "fold_mf.hip", "solve_s.hip", "stencil.hip", "stencil_r2c.hip", "haar.hip", "l1data.hip", "psf_fit.hip", "cnn.hip",
            "api.hip"]
 
 ARCH = "gfx950"

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -207,6 +208,10 @@ struct TvWs {
   float2 *l1sa, *l1sb, *l1sc;
   void *partL, *partW;
   int nbL;
+  // multi-frame data term (sr3d_tv_admm_mf): the frames' LR spectra and shifts
+  int mfF;
+  float2 *mfY;
+  int mfT[kMaxFrames][3];
 };
 
 // Haar levels of SR3D_REG_HAAR (bits 16-19 of the flags; 0 means 1).
@@ -221,7 +226,9 @@ int haar_levels(int flags) {
 size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   Carve c{base, 0};
   L->nbStile = stencil_plan(g.S, g.N, g.M).blocks;
-  L->nbSrow = g.sp.fused && stencil_r2c_supported(g.M) ? stencil_r2c_plan(g.S, g.N, g.M).blocks : 0;
+  L->nbSrow = g.sp.fused && stencil_r2c_fits(g.S, g.N, g.M, g.sp.pitch)
+                  ? stencil_r2c_plan(g.S, g.N, g.M).blocks
+                  : 0;
   L->nbSwav = wavelet_blocks(g.S, g.N, g.M);
   // the one-pass wavelet kernel has the most workgroups at one level
   const int nb_wf = wavelet_fused_blocks(g.S, g.N, g.M, 1);
@@ -259,6 +266,8 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
     L->tab = c.take<int>(g.sp.tab.size());
     L->sdesc = c.take<SolveSArgs>(1);
   }
+  L->mfF = 0;
+  L->mfY = nullptr;
   // l1 data term: LR-sized, about 5 B per HR voxel at d = 8
   L->l1 = false;
   L->nbL = l1_blocks(g.NL);
@@ -315,6 +324,43 @@ SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem 
   a.partial = L.partF; a.ctrl = L.ctrl; a.done = &L.ctrl->done;
   a.a_pos = L.haar ? 1 : 0;
   return a;
+}
+
+// The frames' LR half spectra of a multi-frame solve, after the single-frame
+// workspace.
+size_t mf_extra(const Geometry &g, int nframes) {
+  return ((size_t)nframes * g.nlspec * sizeof(float2) + 511) & ~(size_t)255;
+}
+
+MfArgs make_mf(const Geometry &g, const float2 *lam, const float2 *yf, int nframes,
+               const int (*t)[3]) {
+  MfArgs a{};
+  a.Lam = lam; a.Yf = yf; a.nlspec = g.nlspec; a.F = nframes;
+  for (int f = 0; f < nframes; ++f)
+    for (int c = 0; c < 3; ++c) a.t[f][c] = t[f][c];
+  a.twm = twiddles(g.M); a.twn = twiddles(g.N); a.tws = twiddles(g.S);
+  a.S = g.S; a.N = g.N; a.M = g.M; a.Mh = g.Mh;
+  a.Sl = g.Sl; a.Nl = g.Nl; a.Ml = g.Ml; a.Mlh = g.Mlh;
+  a.dr = g.dr; a.dc = g.dc; a.ds = g.ds;
+  a.ml_eff = g.Ml < g.Mh ? g.Ml : g.Mh;
+  a.scale = (float)(1.0 / (double)g.NH);
+  return a;
+}
+
+// Argument checks of the multi-frame entry points (host, before any HIP call).
+int check_frames(const Geometry &g, int nframes, const float *const *y, const int *shifts) {
+  if (nframes < 1 || nframes > kMaxFrames)
+    return fail(SR3D_ERR_INVALID_ARG, "nframes must be 1.." + std::to_string(kMaxFrames));
+  if (!y || !shifts) return fail(SR3D_ERR_INVALID_ARG, "frames and shifts must be non-NULL");
+  for (int f = 0; f < nframes; ++f) {
+    if (!y[f]) return fail(SR3D_ERR_INVALID_ARG, "a frame pointer is NULL");
+    for (int c = 0; c < 3; ++c)
+      if (shifts[3 * f + c] <= -(1 << 20) || shifts[3 * f + c] >= (1 << 20))
+        return fail(SR3D_ERR_INVALID_ARG, "shifts must lie in (-2^20, 2^20)");
+  }
+  if (!fold_mf_supported(g.D, nframes))
+    return fail(SR3D_ERR_UNSUPPORTED_SIZE, "multi-frame solves take d in {1, 2, 4, 8, 16, 32}");
+  return SR3D_OK;
 }
 
 struct TikWs {
@@ -639,12 +685,21 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
       return e;
   } else {
     if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
-    FoldArgs fa = make_fold(g);
-    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
-    fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
-    fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 1;
-    fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
-    if ((e = fold_solve(fa, fp64, st))) return e;
+    if (L.mfF) {
+      MfArgs ma = make_mf(g, L.lam, L.mfY, L.mfF, L.mfT);
+      ma.W = L.w; ma.X = L.w2;
+      ma.gm = L.g; ma.gn = L.g + g.M; ma.gs = L.g + g.M + g.N;
+      ma.cw = p->mu; ma.coefA = p->mu; ma.tv = 1;
+      ma.partial = L.partF; ma.ctrl = L.ctrl; ma.done = done;
+      if ((e = fold_solve_mf(ma, fp64, st))) return e;
+    } else {
+      FoldArgs fa = make_fold(g);
+      fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+      fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+      fa.cw = p->mu; fa.coefA = p->mu; fa.tv = 1;
+      fa.partial = L.partF; fa.ctrl = L.ctrl; fa.done = done;
+      if ((e = fold_solve(fa, fp64, st))) return e;
+    }
     if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
   }
   AdmmStencilArgs sa{};
@@ -665,16 +720,37 @@ int check_interval(int flags) {
   return k > 0 ? k : 8;
 }
 
+// nframes > 0: the multi-frame data term over frames[0..nframes-1] with HR
+// shifts `shifts` ([nframes][3], host); p->y is not read then.
 int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t ws_bytes,
-           hipStream_t st) {
+           hipStream_t st, int nframes = 0, const float *const *frames = nullptr,
+           const int *shifts = nullptr) {
   Geometry g;
   int rc = check_problem(p, flags, &g);
   if (rc) return rc;
+  if (nframes > 0) {
+    if ((rc = check_frames(g, nframes, frames, shifts))) return rc;
+    if (flags & (SR3D_REG_HAAR | SR3D_WARM_DUAL | SR3D_DATA_L1))
+      return fail(SR3D_ERR_INVALID_ARG,
+                  "multi-frame solves exclude SR3D_REG_HAAR, SR3D_WARM_DUAL and SR3D_DATA_L1");
+  }
   TvWs L;
-  const size_t need = tv_layout(g, nullptr, &L);
+  const size_t base_need = tv_layout(g, nullptr, &L);
+  const size_t need = base_need + (nframes > 0 ? mf_extra(g, nframes) : 0);
   if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
   tv_layout(g, reinterpret_cast<char *>(ws), &L);
   tv_choose_path(g, flags, &L);
+  if (nframes > 0) {
+    // the multi-frame fold runs on the natural spectrum
+    L.mfF = nframes;
+    L.mfY = reinterpret_cast<float2 *>(reinterpret_cast<char *>(ws) + base_need);
+    for (int f = 0; f < nframes; ++f)
+      for (int c = 0; c < 3; ++c) L.mfT[f][c] = shifts[3 * f + c];
+    L.fused = false;
+    L.fsten = false;
+    L.nbF = L.nbFold;
+    L.nbS = L.nbStile;
+  }
   Ctrl *hc = host_ctrl();
   if (!hc) return fail(SR3D_ERR_HIP, "hipHostMalloc failed");
   SR3D_TRY(ensure_device_tables(), "twiddle tables");
@@ -684,6 +760,9 @@ int run_tv(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, size_t
   t_prof.override_stage = prof.on ? kStSetup : -1;
   SR3D_TRY(tv_setup(g, L, p, nu[0], flags, st), "tv setup");
   if (L.l1) SR3D_TRY(l1_setup(g, L, p, nu[1], st), "l1 data setup");
+  for (int f = 0; f < L.mfF; ++f)
+    SR3D_TRY(fft3d_forward(frames[f], L.mfY + (size_t)f * g.nlspec, g.Sl, g.Nl, g.Ml, nullptr, st),
+             "frame spectra");
   t_prof.override_stage = -1;
   int K = check_interval(flags);
   if (flags & SR3D_USE_GRAPH) {
@@ -879,7 +958,8 @@ size_t batch_workspace(const sr3d_problem *p, int count, int flags, std::vector<
   std::vector<char> fz(count), fs(count), none(count, 0);
   for (int i = 0; i < count; ++i) {
     fz[i] = (*gs)[i].sp.fused ? 1 : 0;
-    fs[i] = fz[i] && stencil_r2c_supported((*gs)[i].M) ? 1 : 0;
+    const Geometry &gi = (*gs)[i];
+    fs[i] = fz[i] && stencil_r2c_fits(gi.S, gi.N, gi.M, gi.sp.pitch) ? 1 : 0;
   }
   const bool unfused = (flags & SR3D_UNFUSED) != 0, separate = (flags & SR3D_SEPARATE_R2C) != 0;
   BatchPlan other;
@@ -1207,6 +1287,81 @@ hipError_t scratch_address(char **out) {
   return hipSuccess;
 }
 
+// PSF fit workspace: the HR half spectrum of x, the LR half spectrum of y,
+// the per-axis kernel tables, the per-workgroup partial sums and the totals.
+struct PsfWs {
+  float2 *X, *Yh;
+  float *tab;
+  double *part, *out;
+};
+
+size_t psf_fit_layout(const Geometry &g, char *base, PsfWs *L) {
+  Carve c{base, 0};
+  PsfWs tmp;
+  PsfWs *w = L ? L : &tmp;
+  w->X = c.take<float2>(g.nspec);
+  w->Yh = c.take<float2>(g.nlspec);
+  w->tab = c.take<float>((size_t)2 * (g.M + g.N + g.S));
+  w->part = c.take<double>((size_t)psf_fit_nsums() * psf_fit_blocks(g.nlspec));
+  w->out = c.take<double>((size_t)psf_fit_nsums());
+  return c.off + 256;
+}
+
+// DFT of the symmetric sampled Gaussian g_i = exp(-i^2/(2 s^2)) / sum
+// (|i| <= R, wrapped onto a circle of n points) and its derivative with
+// respect to s, in FP64: l(k) = sum_i g_i cos(2 pi k i / n),
+// dg_i/ds = g_i (i^2 - E[j^2]) / s^3.
+void gaussian_dft(int n, double s, int R, float *l, float *dl) {
+  std::vector<double> g(2 * R + 1);
+  double W = 0.0, m2 = 0.0;
+  for (int i = -R; i <= R; ++i) {
+    g[i + R] = exp(-(double)i * i / (2.0 * s * s));
+    W += g[i + R];
+  }
+  for (int i = -R; i <= R; ++i) {
+    g[i + R] /= W;
+    m2 += g[i + R] * i * i;
+  }
+  for (int k = 0; k < n; ++k) {
+    double a = 0.0, b = 0.0;
+    for (int i = -R; i <= R; ++i) {
+      const long ki = ((long)k * i) % n;
+      const double cs = cos(2.0 * M_PI * (double)ki / (double)n);
+      a += g[i + R] * cs;
+      b += g[i + R] * ((double)i * i - m2) / (s * s * s) * cs;
+    }
+    l[k] = (float)a;
+    dl[k] = (float)b;
+  }
+}
+
+// Solves the n x n system A z = b (n <= 4) by Gaussian elimination with
+// partial pivoting; false if singular.
+bool solve_small(int n, const double A[4][4], const double *b, double *z) {
+  double M[4][5];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) M[i][j] = A[i][j];
+    M[i][n] = b[i];
+  }
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+    if (!(fabs(M[p][c]) > 0.0)) return false;
+    for (int j = 0; j <= n; ++j) std::swap(M[c][j], M[p][j]);
+    for (int r = c + 1; r < n; ++r) {
+      const double f = M[r][c] / M[c][c];
+      for (int j = c; j <= n; ++j) M[r][j] -= f * M[c][j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = M[i][n];
+    for (int j = i + 1; j < n; ++j) t -= M[i][j] * z[j];
+    z[i] = t / M[i][i];
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1224,7 +1379,7 @@ size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
   size_t total = 0;
   const int n = (op == SR3D_OP_BATCH) ? count : 1;
   for (int i = 0; i < n; ++i) {
-    const sr3d_dims *psf = (op == SR3D_OP_FFT) ? nullptr : &p[i].psf_dims;
+    const sr3d_dims *psf = (op == SR3D_OP_FFT || op == SR3D_OP_PSF_FIT) ? nullptr : &p[i].psf_dims;
     sr3d_rate r = p[i].rate;
     if (op == SR3D_OP_FFT) r = sr3d_rate{1, 1, 1};
     if (check_geometry(p[i].hr, r, psf, &g) != SR3D_OK) return 0;
@@ -1237,6 +1392,15 @@ size_t sr3d_workspace_size(int op, const sr3d_problem *p, int count) {
       case SR3D_OP_BATCH: b = tv_layout(g, nullptr, &tv); break;
       case SR3D_OP_DEGRADE: b = degrade_layout(g, nullptr, &tk); break;
       case SR3D_OP_FFT: b = 0; break;
+      case SR3D_OP_PSF_FIT: b = psf_fit_layout(g, nullptr, nullptr); break;
+      case SR3D_OP_TIKHONOV_MF:
+        if (count < 1 || count > kMaxFrames) return 0;
+        b = tik_layout(g, nullptr, &tk) + mf_extra(g, count);
+        break;
+      case SR3D_OP_TV_ADMM_MF:
+        if (count < 1 || count > kMaxFrames) return 0;
+        b = tv_layout(g, nullptr, &tv) + mf_extra(g, count);
+        break;
       default: return 0;
     }
     if (op == SR3D_OP_BATCH) total = b > total ? b : total;
@@ -1280,6 +1444,49 @@ int sr3d_tv_admm(const sr3d_problem *p, int flags, sr3d_stats *stats, void *ws, 
   return run_tv(p, flags, stats, ws, ws_bytes, st);
 }
 
+int sr3d_tv_admm_mf(const sr3d_problem *p, int nframes, const float *const *y, const int *shifts,
+                    int flags, sr3d_stats *stats, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p) return fail(SR3D_ERR_INVALID_ARG, "problem is NULL");
+  if (!y || nframes < 1) return fail(SR3D_ERR_INVALID_ARG, "frames must be non-NULL");
+  sr3d_problem q = *p;
+  q.y = y[0];  // the single-frame checks; the frames themselves are read below
+  return run_tv(&q, flags, stats, ws, ws_bytes, st, nframes, y, shifts);
+}
+
+int sr3d_tikhonov_mf(sr3d_dims hr, sr3d_rate rate, int nframes, const float *const *y,
+                     const int *shifts, const float *psf, sr3d_dims psf_dims, const float *xbar,
+                     float lambda, float *x, void *ws, size_t ws_bytes, hipStream_t st) {
+  Geometry g;
+  int rc = check_tikhonov(hr, rate, (y && nframes > 0) ? y[0] : nullptr, psf, psf_dims, xbar,
+                          lambda, x, &g);
+  if (rc) return rc;
+  if ((rc = check_frames(g, nframes, y, shifts))) return rc;
+  for (int f = 0; f < nframes; ++f)
+    if (x == y[f]) return fail(SR3D_ERR_INVALID_ARG, "x aliases an input");
+  TikWs L;
+  const size_t base_need = tik_layout(g, nullptr, &L);
+  const size_t need = base_need + mf_extra(g, nframes);
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  tik_layout(g, reinterpret_cast<char *>(ws), &L);
+  float2 *yf = reinterpret_cast<float2 *>(reinterpret_cast<char *>(ws) + base_need);
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(pad_psf(psf, psf_dims.s, psf_dims.n, psf_dims.m, L.real, g.S, g.N, g.M, st), "pad psf");
+  SR3D_TRY(fft3d_forward(L.real, L.lam, g.S, g.N, g.M, nullptr, st), "fft Lambda");
+  for (int f = 0; f < nframes; ++f)
+    SR3D_TRY(fft3d_forward(y[f], yf + (size_t)f * g.nlspec, g.Sl, g.Nl, g.Ml, nullptr, st),
+             "frame spectra");
+  if (xbar) SR3D_TRY(fft3d_forward(xbar, L.w, g.S, g.N, g.M, nullptr, st), "fft xbar");
+  int t[kMaxFrames][3];
+  for (int f = 0; f < nframes; ++f)
+    for (int c = 0; c < 3; ++c) t[f][c] = shifts[3 * f + c];
+  MfArgs ma = make_mf(g, L.lam, yf, nframes, t);
+  ma.W = xbar ? L.w : nullptr; ma.X = L.w2;
+  ma.cw = 2.0f * lambda; ma.coefA = 2.0f * lambda; ma.tv = 0;
+  SR3D_TRY(fold_solve_mf(ma, false, st), "multi-frame fold solve");
+  SR3D_TRY(fft3d_inverse(L.w2, x, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
+  return SR3D_OK;
+}
+
 int sr3d_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, void *ws,
                size_t ws_bytes, hipStream_t st) {
   return run_batch(p, count, flags, stats, ws, ws_bytes, st);
@@ -1302,6 +1509,116 @@ int sr3d_degrade(sr3d_dims hr, sr3d_rate rate, const float *x, const float *psf,
   SR3D_TRY(spectrum_mul(L.w, L.lam, (size_t)g.nspec, (float)(1.0 / (double)g.NH), st), "multiply");
   SR3D_TRY(fft3d_inverse(L.w, L.real, g.S, g.N, g.M, 1.0f, nullptr, st), "inverse fft");
   SR3D_TRY(decimate(L.real, y, g.S, g.N, g.M, g.dr, g.dc, g.ds, st), "decimate");
+  return SR3D_OK;
+}
+
+int sr3d_psf_fit(sr3d_dims hr, sr3d_rate rate, const float *x, const float *y, const int radius[3],
+                 const double sigma0[3], int max_iter, double tol, sr3d_psf_fit_result *res,
+                 void *ws, size_t ws_bytes, hipStream_t st) {
+  Geometry g;
+  int rc = check_geometry(hr, rate, nullptr, &g);
+  if (rc) return rc;
+  if (!x || !y || !radius || !sigma0 || !res) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
+  for (int a = 0; a < 3; ++a) {
+    if (radius[a] < 0 || radius[a] > 4096) return fail(SR3D_ERR_INVALID_ARG, "radius out of range");
+    if (!(sigma0[a] > 0.0) || !isfinite(sigma0[a]))
+      return fail(SR3D_ERR_INVALID_ARG, "sigma0 must be finite and > 0");
+  }
+  if (max_iter < 1 || !(tol >= 0.0)) return fail(SR3D_ERR_INVALID_ARG, "max_iter >= 1, tol >= 0");
+  if (g.NL < 2) return fail(SR3D_ERR_INVALID_ARG, "the LR volume needs more than one voxel");
+  PsfWs L;
+  const size_t need = psf_fit_layout(g, nullptr, nullptr);
+  if (!ws || ws_bytes < need) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
+  psf_fit_layout(g, reinterpret_cast<char *>(ws), &L);
+  SR3D_TRY(ensure_device_tables(), "twiddle tables");
+  SR3D_TRY(fft3d_forward(x, L.X, g.S, g.N, g.M, nullptr, st), "fft x");
+  SR3D_TRY(fft3d_forward(y, L.Yh, g.Sl, g.Nl, g.Ml, nullptr, st), "fft y");
+  float2 y0;
+  SR3D_TRY(hipMemcpyAsync(&y0, L.Yh, sizeof y0, hipMemcpyDeviceToHost, st), "copy Y0");
+  const int n_ax[3] = {g.M, g.N, g.S};
+  const int ntab = g.M + g.N + g.S;
+  std::vector<float> tab((size_t)2 * ntab);
+  double sums[17];
+  int passes = 0;
+  // One pass: f, the Gauss-Newton matrix and right-hand side at theta.
+  auto evaluate = [&](const double *th, double *f, double G[4][4], double *bv) -> hipError_t {
+    int off = 0;
+    for (int a = 0; a < 3; ++a) {
+      gaussian_dft(n_ax[a], th[a], radius[a], tab.data() + off, tab.data() + ntab + off);
+      off += n_ax[a];
+    }
+    hipError_t e = hipMemcpyAsync(L.tab, tab.data(), sizeof(float) * tab.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (!e) e = psf_fit_sums(L.X, L.Yh, L.tab, (float)th[3], g.S, g.N, g.M, g.dr, g.dc, g.ds,
+                             L.part, L.out, st);
+    if (!e) e = hipMemcpyAsync(sums, L.out, sizeof sums, hipMemcpyDeviceToHost, st);
+    if (!e) e = hipStreamSynchronize(st);
+    if (e) return e;
+    ++passes;
+    const double inl = 1.0 / (double)g.NL;
+    int q = 0;
+    for (int u = 0; u < 4; ++u)
+      for (int v = u; v < 4; ++v) G[u][v] = G[v][u] = sums[q++] * inl;
+    for (int u = 0; u < 4; ++u) bv[u] = sums[10 + u] * inl;
+    *f = 0.5 * sums[14] * inl;
+    return hipSuccess;
+  };
+  // theta = (sigma_m, sigma_n, sigma_s, alpha); alpha starts at its
+  // least-squares value for sigma0 (from a pass at alpha = 1, where
+  // Re(m^H Y) = Jtr_alpha + JtJ_alpha,alpha).
+  double th[4] = {sigma0[0], sigma0[1], sigma0[2], 1.0};
+  double f, G[4][4], bv[4];
+  SR3D_TRY(evaluate(th, &f, G, bv), "psf fit pass");
+  if (G[3][3] > 0.0) th[3] = (bv[3] + G[3][3]) / G[3][3];
+  SR3D_TRY(evaluate(th, &f, G, bv), "psf fit pass");
+  double m0 = sums[15];  // real part of m_0 at the accepted theta
+  // Levenberg-Marquardt on the Gauss-Newton model.
+  double lam = 1e-3;
+  bool converged = false;
+  for (int it = 0; it < max_iter && !converged; ++it) {
+    bool stepped = false;
+    for (int tries = 0; tries < 12 && !stepped && !converged; ++tries) {
+      double A[4][4], z[4], tn[4], fn, Gn[4][4], bn[4];
+      for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) A[u][v] = G[u][v] + (u == v ? lam * G[u][u] : 0.0);
+      if (!solve_small(4, A, bv, z)) {
+        lam *= 10.0;
+        continue;
+      }
+      double step = 0.0;
+      for (int u = 0; u < 4; ++u) {
+        tn[u] = th[u] + z[u];
+        if (u < 3 && tn[u] < 0.05) tn[u] = 0.05;
+        step = fmax(step, fabs(tn[u] - th[u]) / fmax(fabs(th[u]), 1e-3));
+      }
+      SR3D_TRY(evaluate(tn, &fn, Gn, bn), "psf fit pass");
+      if (fn <= f) {
+        const double df = f - fn;
+        for (int u = 0; u < 4; ++u) {
+          th[u] = tn[u];
+          bv[u] = bn[u];
+          for (int v = 0; v < 4; ++v) G[u][v] = Gn[u][v];
+        }
+        f = fn;
+        m0 = sums[15];
+        lam = fmax(lam / 3.0, 1e-12);
+        stepped = true;
+        if (step <= tol || df <= 1e-15 * fn) converged = true;
+      } else {
+        lam *= 4.0;
+        // no decrease from a step below the tolerance: at the minimum
+        if (step <= tol) converged = true;
+      }
+    }
+    if (!stepped) break;
+  }
+  // The offset that zeroes the zero-frequency residual: beta = (Y_0 - alpha m_0) / N_l.
+  for (int a = 0; a < 3; ++a) res->sigma[a] = th[a];
+  res->gain = th[3];
+  res->offset = ((double)y0.x - th[3] * m0) / (double)g.NL;
+  res->objective = f;
+  res->passes = passes;
+  res->converged = converged ? 1 : 0;
   return SR3D_OK;
 }
 

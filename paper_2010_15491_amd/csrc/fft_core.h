@@ -36,13 +36,14 @@ constexpr int tile_lines(int N, int E) {
 constexpr int kTileVariants = 3;
 constexpr int kTileElems[kTileVariants] = {2048, 4096, 8192};
 
-// The FFT arithmetic below is never contracted into FMAs: whether the
-// compiler would fuse a product into a later sum depends on the surrounding
+// The FFT arithmetic below is never contracted into FMAs by the compiler:
+// whether it would fuse a product into a later sum depends on the surrounding
 // code (unrolling, tile shape), and every kernel that runs these transforms
-// must produce the same bits for the same line.
+// must produce the same bits for the same line. The fused multiply-adds it
+// does use are explicit (fmaf), so they are the same in every kernel.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 #pragma clang fp contract(off)
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -63,7 +64,7 @@ template <> __device__ __forceinline__ void butterfly<3>(float2 *v) {
   const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
   float2 s = cadd(v[1], v[2]);
   float2 d = csub(v[1], v[2]);
-  float2 t = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
+  float2 t = make_float2(fmaf(-0.5f, s.x, v[0].x), fmaf(-0.5f, s.y, v[0].y));
   float2 e = make_float2(h * d.y, -h * d.x);  // -i h d
   v[0] = cadd(v[0], s);
   v[1] = cadd(t, e);
@@ -159,8 +160,8 @@ __device__ __forceinline__ float2 r2c_post(float2 zk, float2 zm, float2 wk) {
 #pragma clang fp contract(off)
   const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
   const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-  const float2 wo = cmul(wk, o);
-  return make_float2(e.x + wo.x, e.y + wo.y);
+  // e + wk o
+  return make_float2(fmaf(wk.x, o.x, fmaf(-wk.y, o.y, e.x)), fmaf(wk.x, o.y, fmaf(wk.y, o.x, e.y)));
 }
 
 template <int N>

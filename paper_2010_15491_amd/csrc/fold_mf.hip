@@ -1,0 +1,318 @@
+// Multi-frame fold / solve / unfold (3D multi-frame SR, which the paper's
+// conclusion names as future work). F LR frames y_f = D S_f H x + n_f of one
+// HR volume, S_f a circular shift by t_f HR voxels ((S_f z)[i] = z[i + t_f]).
+// With F(S_f z)_k = w_f(k) Z_k, w_f(k) = exp(2 pi i k . t_f / n), eq. (8)
+// turns the normal equations of eq. (6) (and of Algorithm 1 step 5a) into one
+// d x d system per alias group j with one rank-one term per frame:
+//   (1/d) sum_f conj(v_f) v_f^T X + diag(A) X = B,   v_f,a = w_f(k_a) Lambda_a,
+//   B_a = sum_f conj(v_f,a) Y_f,j + c W_a.
+// Woodbury with the F x F matrix Q = d I + V^T A^-1 conj(V) gives
+//   Q t = V^T A^-1 B,   X_a = (B_a - sum_f conj(v_f,a) t_f) / A_a,
+// solved in FP64 (complex Cholesky) by the thread that owns the group. In a
+// TV solve the zero-frequency member has A = 0; that group is solved by the
+// Schur complement of member 0, with the same Woodbury solve for the rest.
+// The phase factors come from the FFT twiddle tables: w = conj(tw_n[k t mod n]).
+#include "sr3d_internal.h"
+
+namespace sr3d {
+
+namespace {
+
+struct zd {
+  double x, y;
+};
+__device__ __forceinline__ zd zmul(zd a, zd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ zd zconj(zd a) { return {a.x, -a.y}; }
+__device__ __forceinline__ zd zadd(zd a, zd b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ zd zsub(zd a, zd b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ zd zscale(zd a, double s) { return {a.x * s, a.y * s}; }
+__device__ __forceinline__ zd zf(float2 a) { return {(double)a.x, (double)a.y}; }
+
+// exp(+2 pi i k t / n) from the table tw[k] = exp(-2 pi i k / n)
+// (0 <= k < n <= 1024, |t| < 2^20, so k t fits 32 bits).
+__device__ __forceinline__ float2 phase(const float2 *tw, int n, int k, int t) {
+  int kt = (k * t) % n;
+  kt += kt < 0 ? n : 0;
+  const float2 w = tw[kt];
+  return make_float2(w.x, -w.y);
+}
+__device__ __forceinline__ float2 fmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Solves Q z = b for the Hermitian positive definite FM x FM matrix Q (upper
+// triangle used) by a complex Cholesky factorisation Q = R^H R, in place.
+// Frames beyond the call's F enter as rows d e_f with b_f = 0 (solution 0),
+// so the loops run over all FM and unroll.
+template <int FM>
+__device__ __forceinline__ void chol_solve(zd (&Q)[FM][FM], zd (&b)[FM]) {
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    double di = Q[i][i].x;
+#pragma unroll
+    for (int k = 0; k < i; ++k) di -= Q[k][i].x * Q[k][i].x + Q[k][i].y * Q[k][i].y;
+    const double rii = sqrt(fmax(di, 0.0));
+    const double inv = rii > 0.0 ? 1.0 / rii : 0.0;
+    Q[i][i] = {rii, inv};  // keep 1/R_ii in the imaginary slot
+#pragma unroll
+    for (int j = i + 1; j < FM; ++j) {
+      zd s = Q[i][j];
+#pragma unroll
+      for (int k = 0; k < i; ++k) s = zsub(s, zmul(zconj(Q[k][i]), Q[k][j]));
+      Q[i][j] = zscale(s, inv);
+    }
+  }
+  // R^H y = b
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    zd s = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = zsub(s, zmul(zconj(Q[k][i]), b[k]));
+    b[i] = zscale(s, Q[i][i].y);
+  }
+  // R z = y
+#pragma unroll
+  for (int i = FM - 1; i >= 0; --i) {
+    zd s = b[i];
+#pragma unroll
+    for (int k = i + 1; k < FM; ++k) s = zsub(s, zmul(Q[i][k], b[k]));
+    b[i] = zscale(s, Q[i][i].y);
+  }
+}
+
+template <int D, int FM, typename Acc>
+__global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
+  if (a.done && *a.done) return;
+  __shared__ Acc sh[kThreads / 64];
+  const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
+  const long g = (long)blockIdx.x * kThreads + threadIdx.x;
+  const int F = a.F;
+  Acc resid = 0;
+  if (g < ngroups) {
+    const int jm = (int)(g % a.ml_eff);
+    const long r1 = g / a.ml_eff;
+    const int jn = (int)(r1 % a.Nl);
+    const int js = (int)(r1 / a.Nl);
+    // LR spectra of the frames at j (stored half, mirrored otherwise)
+    zd Y[FM];
+    {
+      long id;
+      bool mir = false;
+      if (jm < a.Mlh) {
+        id = ((long)js * a.Nl + jn) * a.Mlh + jm;
+      } else {
+        id = ((long)((a.Sl - js) % a.Sl) * a.Nl + (a.Nl - jn) % a.Nl) * a.Mlh + (a.Ml - jm);
+        mir = true;
+      }
+#pragma unroll
+      for (int f = 0; f < FM; ++f) {
+        Y[f] = {0.0, 0.0};
+        if (f < F) {
+          const float2 y = a.Yf[(long)f * a.nlspec + id];
+          Y[f] = {(double)y.x, mir ? -(double)y.y : (double)y.y};
+        }
+      }
+    }
+    zd lam[D], B[D];
+    double A[D];
+    int km_[D], kn_[D], ks_[D];
+    long idx[D];
+    bool own[D];
+    int ia = 0, ib = 0, ic = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const int km = jm + ia * a.Ml, kn = jn + ib * a.Nl, ks = js + ic * a.Sl;
+      const bool direct = km < a.Mh;
+      long id;
+      if (direct) id = ((long)ks * a.N + kn) * a.Mh + km;
+      else id = ((long)((a.S - ks) % a.S) * a.N + (a.N - kn) % a.N) * a.Mh + (a.M - km);
+      float2 l = a.Lam[id];
+      float2 w = a.W ? a.W[id] : make_float2(0.f, 0.f);
+      if (!direct) {
+        l.y = -l.y;
+        w.y = -w.y;
+      }
+      lam[q] = zf(l);
+      A[q] = a.tv ? (double)a.coefA * ((double)a.gs[ks] + (double)a.gn[kn] + (double)a.gm[km])
+                  : (double)a.coefA;
+      zd b = zscale(zf(w), (double)a.cw);
+#pragma unroll
+      for (int f = 0; f < FM; ++f) {
+        if (f < F) {
+          const float2 ph = fmul(fmul(phase(a.twm, a.M, km, a.t[f][0]), phase(a.twn, a.N, kn, a.t[f][1])),
+                                 phase(a.tws, a.S, ks, a.t[f][2]));
+          b = zadd(b, zmul(zconj(zmul(zf(ph), lam[q])), Y[f]));
+        }
+      }
+      B[q] = b;
+      km_[q] = km; kn_[q] = kn; ks_[q] = ks;
+      idx[q] = id;
+      own[q] = direct;
+      if (++ia == a.dr) {
+        ia = 0;
+        if (++ib == a.dc) {
+          ib = 0;
+          ++ic;
+        }
+      }
+    }
+    auto v_of = [&](int f, int q) {
+      const float2 ph = fmul(fmul(phase(a.twm, a.M, km_[q], a.t[f][0]),
+                                  phase(a.twn, a.N, kn_[q], a.t[f][1])),
+                             phase(a.tws, a.S, ks_[q], a.t[f][2]));
+      return zmul(zf(ph), lam[q]);
+    };
+    // Woodbury over members q0 .. D-1 (A > 0 there): Q t = V^T A^-1 z.
+    auto woodbury = [&](int q0, const zd *z, zd *out) {
+      zd Q[FM][FM], t[FM];
+#pragma unroll
+      for (int f = 0; f < FM; ++f) {
+        t[f] = {0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < FM; ++h) Q[f][h] = {f == h ? (double)D : 0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        if (q < q0) continue;
+        const double ia_ = 1.0 / A[q];
+        zd v[FM];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) v[f] = f < F ? v_of(f, q) : zd{0.0, 0.0};
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+          t[f] = zadd(t[f], zscale(zmul(v[f], z[q]), ia_));
+#pragma unroll
+          for (int h = f; h < FM; ++h) Q[f][h] = zadd(Q[f][h], zscale(zmul(v[f], zconj(v[h])), ia_));
+        }
+      }
+      chol_solve<FM>(Q, t);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        if (q < q0) continue;
+        zd s = z[q];
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+          if (f < F) s = zsub(s, zmul(zconj(v_of(f, q)), t[f]));
+        out[q] = zscale(s, 1.0 / A[q]);
+      }
+    };
+    zd X[D];
+    if (a.tv && g == 0) {
+      // Zero-frequency group: member 0 has A = 0. Schur complement of member
+      // 0 with K_rr = diag(A_r) + (1/d) conj(V_r) V_r^T (Woodbury):
+      //   X_0 = (B_0 - K_0r K_rr^-1 B_r) / (k_00 - K_0r K_rr^-1 K_r0),
+      //   X_r = K_rr^-1 (B_r - K_r0 X_0).
+      zd kr0[D], u1[D], u2[D];
+      double k00 = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        kr0[q] = {0.0, 0.0};
+        u1[q] = u2[q] = {0.0, 0.0};
+      }
+#pragma unroll
+      for (int f = 0; f < FM; ++f) {
+        if (f >= F) continue;
+        const zd v0 = v_of(f, 0);
+        k00 += (v0.x * v0.x + v0.y * v0.y) / (double)D;
+#pragma unroll
+        for (int q = 1; q < D; ++q) kr0[q] = zadd(kr0[q], zscale(zmul(zconj(v_of(f, q)), v0), 1.0 / D));
+      }
+      woodbury(1, B, u1);    // K_rr^-1 B_r
+      woodbury(1, kr0, u2);  // K_rr^-1 K_r0
+      zd num = B[0], den = {k00, 0.0};
+#pragma unroll
+      for (int q = 1; q < D; ++q) {
+        // K_0r = conj(K_r0)^T (K is Hermitian)
+        num = zsub(num, zmul(zconj(kr0[q]), u1[q]));
+        den = zsub(den, zmul(zconj(kr0[q]), u2[q]));
+      }
+      const double dn = den.x * den.x + den.y * den.y;
+      if (!(dn > 0.0)) {
+        a.ctrl->status = SR3D_ERR_SINGULAR;
+        a.ctrl->done = 1;
+#pragma unroll
+        for (int q = 0; q < D; ++q) X[q] = {0.0, 0.0};
+      } else {
+        X[0] = zscale(zmul(num, zconj(den)), 1.0 / dn);
+        zd z[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) z[q] = zsub(B[q], zmul(kr0[q], X[0]));
+        woodbury(1, z, X);
+      }
+    } else {
+      woodbury(0, B, X);
+    }
+    // Data residual of the new x: sum_f |Y_f,j - (1/d) sum_a v_f,a X_a|^2.
+    if (a.partial) {
+      Acc wgt = 1;
+      if (a.ml_eff < a.Ml && jm != 0 && 2 * jm != a.Ml) wgt = 2;
+#pragma unroll
+      for (int f = 0; f < FM; ++f) {
+        if (f >= F) continue;
+        zd m = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < D; ++q) m = zadd(m, zmul(v_of(f, q), X[q]));
+        const zd r = zsub(Y[f], zscale(m, 1.0 / D));
+        resid += wgt * (Acc)(r.x * r.x + r.y * r.y);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (own[q]) a.X[idx[q]] = make_float2((float)(X[q].x * a.scale), (float)(X[q].y * a.scale));
+  }
+  if (a.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) resid += __shfl_xor(resid, off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = resid;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Acc s = 0;
+      for (int i = 0; i < kThreads / 64; ++i) s += sh[i];
+      reinterpret_cast<Acc *>(a.partial)[blockIdx.x] = s;
+    }
+  }
+}
+
+template <int FM, typename Acc>
+hipError_t launch_mf(const MfArgs &a, hipStream_t st) {
+  const int D = a.dr * a.dc * a.ds;
+  const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
+  dim3 g((unsigned)((ngroups + kThreads - 1) / kThreads)), b(kThreads);
+  switch (D) {
+#define SR3D_D(DD)                                                        \
+  case DD:                                                                \
+    hipLaunchKernelGGL((k_fold_solve_mf<DD, FM, Acc>), g, b, 0, st, a);   \
+    break;
+    SR3D_D(1) SR3D_D(2) SR3D_D(4) SR3D_D(8) SR3D_D(16) SR3D_D(32)
+#undef SR3D_D
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fold_mf_supported(int d, int nframes) {
+  return (d == 1 || d == 2 || d == 4 || d == 8 || d == 16 || d == 32) && nframes >= 1 &&
+         nframes <= kMaxFrames;
+}
+
+int fold_mf_blocks(const MfArgs &a) {
+  const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
+  return (int)((ngroups + kThreads - 1) / kThreads);
+}
+
+hipError_t fold_solve_mf(const MfArgs &a, bool fp64, hipStream_t st) {
+  if (!fold_mf_supported(a.dr * a.dc * a.ds, a.F)) return hipErrorInvalidValue;
+  prof_begin(kStFold, st);
+  hipError_t e;
+  if (a.F <= 2) e = fp64 ? launch_mf<2, double>(a, st) : launch_mf<2, float>(a, st);
+  else e = fp64 ? launch_mf<kMaxFrames, double>(a, st) : launch_mf<kMaxFrames, float>(a, st);
+  prof_end(st);
+  return e;
+}
+
+}  // namespace sr3d

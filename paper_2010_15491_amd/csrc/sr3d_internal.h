@@ -183,6 +183,31 @@ struct FoldArgs {
   float2 *dhx;        // LR half spectrum of D H x for the new x (unscaled), or null
 };
 int fold_blocks(const FoldArgs &a);
+
+// Multi-frame fold / solve / unfold (fold_mf.hip): F LR frames of HR-shifted
+// copies, y_f = D S_f H x + n_f, (S_f z)[i] = z[i + t_f].
+constexpr int kMaxFrames = 4;
+struct MfArgs {
+  const float2 *W;    // F Theta (TV) or F xbar (Tikhonov) half spectrum, or null
+  const float2 *Lam;  // Lambda half spectrum
+  const float2 *Yf;   // the frames' LR half spectra, nlspec apart
+  long nlspec;
+  float2 *X;          // output half spectrum (scaled by `scale`)
+  const float *gm, *gn, *gs;
+  const float2 *twm, *twn, *tws;  // exp(-2 pi i k / n) for n = M, N, S
+  int t[kMaxFrames][3];           // shifts (t_m, t_n, t_s) of the frames
+  int F;
+  int S, N, M, Mh, Sl, Nl, Ml, Mlh, dr, dc, ds, ml_eff;
+  float cw, coefA;
+  int tv;
+  float scale;
+  void *partial;      // data-term partial sums, one per workgroup (Acc), or null
+  Ctrl *ctrl;
+  const int *done;
+};
+bool fold_mf_supported(int d, int nframes);
+int fold_mf_blocks(const MfArgs &a);
+hipError_t fold_solve_mf(const MfArgs &a, bool fp64, hipStream_t st);
 hipError_t fold_solve(const FoldArgs &a, bool fp64, hipStream_t st);
 hipError_t dual_init_spectrum(const FoldArgs &a, hipStream_t st);
 hipError_t fold_solve_batch(int D, const FoldArgs *descs, const int2 *items, int nitems, bool fp64,
@@ -263,6 +288,9 @@ hipError_t admm_stencil(const AdmmStencilArgs &a, bool stats, bool fp64, hipStre
 // order kofp, rows `pitch` apart) instead of Theta. a.x and a.nu_in must be
 // non-null; the residual sums are always formed.
 bool stencil_r2c_supported(int M);
+// The fused stencil handles this volume: a supported row length, and every
+// state and spectrum offset within 32 bits.
+bool stencil_r2c_fits(int S, int N, int M, int pitch);
 StencilPlan stencil_r2c_plan(int S, int N, int M);
 hipError_t admm_stencil_r2c(const AdmmStencilArgs &a, float2 *spec, const int *kofp, int pitch,
                             bool fp64, hipStream_t st);
@@ -305,6 +333,15 @@ hipError_t l1_wnorm(const float2 *A, const float2 *B, const float *w, long n, vo
                     const int *done, hipStream_t st);
 hipError_t l1_reduce_test(Ctrl *c, const void *ps, int nbs, const void *pl, int nbl, const void *pw,
                           int nbw, bool fp64, hipStream_t st);
+
+// PSF estimation (psf_fit.hip): one Gauss-Newton pass over the HR half
+// spectrum X of the reference with per-axis kernel tables (l_m | l_n | l_s |
+// dl_m | dl_n | dl_s), leaving psf_fit_nsums() FP64 totals in `out`.
+int psf_fit_blocks(long nlspec);
+int psf_fit_nsums();
+hipError_t psf_fit_sums(const float2 *X, const float2 *Yh, const float *tab, float alpha, int S,
+                        int N, int M, int dr, int dc, int ds, double *part, double *out,
+                        hipStream_t st);
 
 // Setup kernels.
 hipError_t pad_psf(const float *psf, int Ks, int Kn, int Km, float *out, int S, int N, int M,

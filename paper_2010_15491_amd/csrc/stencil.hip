@@ -191,12 +191,7 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
         a.nu_out[v + NT] = q.nn[1];
         a.nu_out[v + 2 * NT] = q.nn[2];
         if (STATS) {
-          const float l2 = q.l[0] * q.l[0] + q.l[1] * q.l[1] + q.l[2] * q.l[2];
-          const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
-          acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
-          acc[1] += l2;
-          acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-          acc[3] += tv_term<ANISO>(q.l);  // |(L x)_j|
+          point_stats<ANISO>(q, acc);
         }
       }
     }
@@ -223,8 +218,8 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
       if (pval[k]) {
         a.theta[sb + poff[k]] = ltw;
         if (STATS) {
-          acc[4] += ltu * ltu;
-          acc[5] += ltd * ltd;
+          acc[4] = fmaf(ltu, ltu, acc[4]);
+          acc[5] = fmaf(ltd, ltd, acc[5]);
         }
       }
     }

@@ -1,9 +1,10 @@
 // Pointwise pieces of the ADMM stencil (Algorithm 1 steps 5b, 5c) shared by
 // the stencil kernels.
 //
-// Included after the file's `#pragma clang fp contract(off)`: every product
-// and sum is rounded on its own, so all kernels built from these pieces (and
-// the resume path) produce the same bits for the same point.
+// Included after the file's `#pragma clang fp contract(off)`: the compiler
+// fuses no product into a sum, and the fused multiply-adds used here are
+// explicit (fmaf), so all kernels built from these pieces (and the resume
+// path) produce the same bits for the same point.
 #pragma once
 
 #include "sr3d_internal.h"
@@ -27,6 +28,30 @@ __device__ __forceinline__ void block_reduce_n(T *v, int n, T *sh /* [n][4] */) 
     for (int q = 0; q < n; ++q) v[q] = sh[q * 4 + 0] + sh[q * 4 + 1] + sh[q * 4 + 2] + sh[q * 4 + 3];
 }
 
+// Global loads and stores at a 32-bit byte offset from a base pointer held in
+// scalar registers (the hardware's scalar-base addressing: no 64-bit address
+// arithmetic per lane). Callers keep every offset below 4 GiB.
+__device__ __forceinline__ float ld_off(const float *base, uint32_t i) {
+  return *(__attribute__((address_space(1))) const float *)(
+      (__attribute__((address_space(1))) const char *)base + (i << 2));
+}
+__device__ __forceinline__ void st_off(float *base, uint32_t i, float v) {
+  *(__attribute__((address_space(1))) float *)((__attribute__((address_space(1))) char *)base +
+                                               (i << 2)) = v;
+}
+__device__ __forceinline__ void st_off2(float2 *base, uint32_t i, float2 v) {
+  const uint64_t bits = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+  *(__attribute__((address_space(1))) uint64_t *)((__attribute__((address_space(1))) char *)base +
+                                                  (i << 3)) = bits;
+}
+
+// The value of lane (l - 1) mod 64 of the wavefront: a DPP rotation of the
+// whole wavefront right by one lane (no LDS traffic).
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C /* wave_ror:1 */,
+                                                    0xF, 0xF, false));
+}
+
 // Workgroup b of nb is dispatched to XCD b % 8; give every XCD a contiguous
 // range of tiles so neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -40,8 +65,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // root; a = 0 gives u = 0.
 __device__ __forceinline__ void shrink3(float a0, float a1, float a2, float thr, float &u0,
                                         float &u1, float &u2) {
-  const float n2 = a0 * a0 + a1 * a1 + a2 * a2;
-  const float s = n2 > 0.f ? fmaxf(1.f - thr * __builtin_amdgcn_rsqf(n2), 0.f) : 0.f;
+  const float n2 = fmaf(a2, a2, fmaf(a1, a1, a0 * a0));
+  const float s = n2 > 0.f ? fmaxf(fmaf(-thr, __builtin_amdgcn_rsqf(n2), 1.f), 0.f) : 0.f;
   u0 = a0 * s;
   u1 = a1 * s;
   u2 = a2 * s;
@@ -63,18 +88,6 @@ __device__ __forceinline__ void shrink_tv(float a0, float a1, float a2, float th
     u2 = shrink1(a2, thr);
   } else {
     shrink3(a0, a1, a2, thr, u0, u1, u2);
-  }
-}
-
-// The regulariser's term of one voxel from (L x)_j: ||.||_2 (isotropic) or
-// ||.||_1 (anisotropic).
-template <bool ANISO>
-__device__ __forceinline__ float tv_term(const float *l) {
-  if constexpr (ANISO) {
-    return fabsf(l[0]) + fabsf(l[1]) + fabsf(l[2]);
-  } else {
-    const float l2 = l[0] * l[0] + l[1] * l[1] + l[2] * l[2];
-    return l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;
   }
 }
 
@@ -108,6 +121,22 @@ __device__ __forceinline__ void point_update_at(const float *xc, const float *xn
     q.w[c] = q.u[c] - q.d[c];
     q.du[c] = q.u[c] - uo[c];
   }
+}
+
+// The point's terms of the residual sums: |Lx - u'|^2, |Lx|^2, |u'|^2 and
+// the regulariser's |(Lx)_j| (accumulated with fused multiply-adds; these
+// sums feed only the stopping test and the objective).
+template <bool ANISO>
+__device__ __forceinline__ void point_stats(const PointQ &q, float *acc) {
+  const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
+  acc[0] = fmaf(r2, r2, fmaf(r1, r1, fmaf(r0, r0, acc[0])));
+  const float l2 = fmaf(q.l[2], q.l[2], fmaf(q.l[1], q.l[1], q.l[0] * q.l[0]));
+  acc[1] += l2;
+  acc[2] = fmaf(q.u[2], q.u[2], fmaf(q.u[1], q.u[1], fmaf(q.u[0], q.u[0], acc[2])));
+  if constexpr (ANISO)
+    acc[3] += fabsf(q.l[0]) + fabsf(q.l[1]) + fabsf(q.l[2]);
+  else
+    acc[3] += l2 > 0.f ? l2 * __builtin_amdgcn_rsqf(l2) : 0.f;
 }
 
 }  // namespace sr3d

@@ -60,8 +60,12 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
   __shared__ Acc sh[6 * 4];
 
   const int S = a.S, N = a.N;
-  const long NT = (long)S * N * M;
-  const long plane = (long)N * M;
+  // Element offsets below 2^30 (the host checks the volume), so byte offsets
+  // fit 32 bits; the three state components have base pointers of their own.
+  const uint32_t NT = (uint32_t)S * N * M;
+  const uint32_t plane = (uint32_t)N * M;
+  const float *const nui0 = a.nu_in, *const nui1 = a.nu_in + NT, *const nui2 = a.nu_in + 2 * (size_t)NT;
+  float *const nuo0 = a.nu_out, *const nuo1 = a.nu_out + NT, *const nuo2 = a.nu_out + 2 * (size_t)NT;
   const int tn = b % pl.tiles_n, ch = b / pl.tiles_n;
   const int n0 = tn * SR_ROWS;
   const int s0 = ch * pl.L;
@@ -104,10 +108,12 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
   const int fn = ((n0 - 1) % N + N) % N;
 
   auto ring_fetch = [&](int sp, float *xr) {
-    const long base = (long)(((sp % S) + S) % S) * plane;
+    const uint32_t base = (uint32_t)(((sp % S) + S) % S) * plane;
 #pragma unroll
     for (int k = 0; k < XPT; ++k)
-      xr[k] = (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) ? a.x[base + ring_off(k)] : 0.f;
+      xr[k] = (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE)
+                  ? ld_off(a.x, base + (uint32_t)ring_off(k))
+                  : 0.f;
   };
   auto ring_store = [&](int buf, const float *xr) {
 #pragma unroll
@@ -116,21 +122,21 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
   };
   // nu_old at the own points (CH) and the row n0-1 points (FPT) of plane sp
   auto nu_fetch = [&](int sp, float (*o)[3]) {
-    const long sb = (long)(((sp % S) + S) % S) * plane;
+    const uint32_t sb = (uint32_t)(((sp % S) + S) % S) * plane;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const long v = sb + (long)gn * M + lane + 64 * c;
-      o[c][0] = a.nu_in[v];
-      o[c][1] = a.nu_in[v + NT];
-      o[c][2] = a.nu_in[v + 2 * NT];
+      const uint32_t v = sb + (uint32_t)(gn * M + lane + 64 * c);
+      o[c][0] = ld_off(nui0, v);
+      o[c][1] = ld_off(nui1, v);
+      o[c][2] = ld_off(nui2, v);
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       const int m = tid + kThreads * j;
-      const long v = sb + (long)fn * M + (m < M ? m : 0);
-      o[CH + j][0] = a.nu_in[v];
-      o[CH + j][1] = a.nu_in[v + NT];
-      o[CH + j][2] = a.nu_in[v + 2 * NT];
+      const uint32_t v = sb + (uint32_t)(fn * M + (m < M ? m : 0));
+      o[CH + j][0] = ld_off(nui0, v);
+      o[CH + j][1] = ld_off(nui1, v);
+      o[CH + j][2] = ld_off(nui2, v);
     }
   };
   // LDS index of the point (ring row rr, m) and of its m and n successors
@@ -175,7 +181,7 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       nu_fetch(sp + 1, nun);
     }
     __syncthreads();
-    const long sb = (long)sp * plane;
+    const uint32_t sb = (uint32_t)sp * plane;
     float mw[CH], md[CH], mu[CH];  // m-components at the own points
     float tw[CH], td[CH], tu[CH];  // s-term minus the point's own sum
 #pragma unroll
@@ -198,16 +204,11 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       pd[c] = q.d[2];
       pu[c] = q.du[2];
       if (rval) {
-        const long v = sb + (long)gn * M + m;
-        a.nu_out[v] = q.nn[0];
-        a.nu_out[v + NT] = q.nn[1];
-        a.nu_out[v + 2 * NT] = q.nn[2];
-        const float l2 = q.l[0] * q.l[0] + q.l[1] * q.l[1] + q.l[2] * q.l[2];
-        const float r0 = q.l[0] - q.u[0], r1 = q.l[1] - q.u[1], r2 = q.l[2] - q.u[2];
-        acc[0] += r0 * r0 + r1 * r1 + r2 * r2;
-        acc[1] += l2;
-        acc[2] += q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2];
-        acc[3] += tv_term<ANISO>(q.l);  // |(L x)_j|
+        const uint32_t v = sb + (uint32_t)(gn * M + m);
+        st_off(nuo0, v, q.nn[0]);
+        st_off(nuo1, v, q.nn[1]);
+        st_off(nuo2, v, q.nn[2]);
+        point_stats<ANISO>(q, acc);
       }
     }
 #pragma unroll
@@ -223,16 +224,16 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       }
     }
     // The m-neighbour (m - 1, wrapping) of lane l in chunk c is lane l - 1 of
-    // chunk c, or lane 63 of chunk c - 1 for lane 0.
+    // chunk c, or lane 63 of chunk c - 1 for lane 0: a rotation of the
+    // wavefront by one lane (lane l receives lane l - 1, lane 0 lane 63).
     float lw[CH], ld[CH], lu[CH];
     {
-      const int src = (lane + 63) & 63;
       float rw[CH], rd[CH], ru[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
-        rw[c] = __shfl(mw[c], src);
-        rd[c] = __shfl(md[c], src);
-        ru[c] = __shfl(mu[c], src);
+        rw[c] = lane_prev(mw[c]);
+        rd[c] = lane_prev(md[c]);
+        ru[c] = lane_prev(mu[c]);
       }
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
@@ -254,8 +255,8 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       const float ltu = (lu[c] + fu[fi]) + tu[c];
       z[2 * ((m >> 1) * TP + row) + (m & 1)] = ltw;
       if (rval) {
-        acc[4] += ltu * ltu;
-        acc[5] += ltd * ltd;
+        acc[4] = fmaf(ltu, ltu, acc[4]);
+        acc[5] = fmaf(ltd, ltd, acc[5]);
       }
     }
 #pragma unroll
@@ -269,8 +270,8 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       const int p = w % MH, t = w / MH;
       if (n0 + t < N) {
         const int k = sperm[p];
-        out[((long)sp * N + n0 + t) * pitch + p] =
-            r2c_post(z2[(k % H) * TP + t], z2[((H - k) % H) * TP + t], stwm[k]);
+        st_off2(out, ((uint32_t)sp * N + n0 + t) * (uint32_t)pitch + p,
+                r2c_post(z2[(k % H) * TP + t], z2[((H - k) % H) * TP + t], stwm[k]));
       }
     }
   }
@@ -329,6 +330,11 @@ bool stencil_r2c_supported(int M) {
     default:
       return false;
   }
+}
+
+bool stencil_r2c_fits(int S, int N, int M, int pitch) {
+  const uint64_t nt = (uint64_t)S * N * M, rows = (uint64_t)S * N;
+  return stencil_r2c_supported(M) && nt * 4 < (1ull << 32) && rows * pitch * 8 < (1ull << 32);
 }
 
 StencilPlan stencil_r2c_plan(int S, int N, int M) {

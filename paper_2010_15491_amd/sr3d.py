@@ -42,9 +42,12 @@ def CHECK_INTERVAL(k):
     return (int(k) & 0xFF) << 8
 
 
-OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT = 1, 2, 3, 4, 5
+OP_TIKHONOV, OP_TV_ADMM, OP_BATCH, OP_DEGRADE, OP_FFT, OP_PSF_FIT = 1, 2, 3, 4, 5, 6
+OP_TIKHONOV_MF, OP_TV_ADMM_MF = 7, 8
+MAX_FRAMES = 4
 
-EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tikhonov_noalloc", "sr3d_tv_admm", "sr3d_batch",
+EXPORTS = ["sr3d_workspace_size", "sr3d_tikhonov", "sr3d_tikhonov_noalloc", "sr3d_tv_admm", "sr3d_psf_fit",
+           "sr3d_tikhonov_mf", "sr3d_tv_admm_mf", "sr3d_batch",
            "sr3d_degrade", "sr3d_rfft3d", "sr3d_irfft3d", "sr3d_cnn_param_count",
            "sr3d_cnn_init", "sr3d_cnn_workspace_size", "sr3d_cnn_forward", "sr3d_cnn_grad",
            "sr3d_cnn_adam", "sr3d_conv3d_workspace_size", "sr3d_conv3d_forward",
@@ -76,6 +79,12 @@ class Problem(ctypes.Structure):
                 ("mu_data", ctypes.c_float)]
 
 
+class PsfFitResult(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double * 3), ("gain", ctypes.c_double),
+                ("offset", ctypes.c_double), ("objective", ctypes.c_double),
+                ("passes", ctypes.c_int), ("converged", ctypes.c_int)]
+
+
 class Sr3dError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -99,6 +108,18 @@ def load():
         lib.sr3d_tikhonov.restype = ci
         lib.sr3d_tikhonov_noalloc.argtypes = [Dims, Rate, vp, vp, Dims, vp, cf, vp, vp]
         lib.sr3d_tikhonov_noalloc.restype = ci
+        lib.sr3d_psf_fit.argtypes = [Dims, Rate, vp, vp, ctypes.POINTER(ctypes.c_int * 3),
+                                     ctypes.POINTER(ctypes.c_double * 3), ci, ctypes.c_double,
+                                     ctypes.POINTER(PsfFitResult), vp, sz, vp]
+        lib.sr3d_psf_fit.restype = ci
+        lib.sr3d_tikhonov_mf.argtypes = [Dims, Rate, ci, ctypes.POINTER(vp),
+                                         ctypes.POINTER(ctypes.c_int), vp, Dims, vp, cf, vp, vp,
+                                         sz, vp]
+        lib.sr3d_tikhonov_mf.restype = ci
+        lib.sr3d_tv_admm_mf.argtypes = [ctypes.POINTER(Problem), ci, ctypes.POINTER(vp),
+                                        ctypes.POINTER(ctypes.c_int), ci, ctypes.POINTER(Stats),
+                                        vp, sz, vp]
+        lib.sr3d_tv_admm_mf.restype = ci
         lib.sr3d_tv_admm.argtypes = [ctypes.POINTER(Problem), ci, ctypes.POINTER(Stats), vp, sz, vp]
         lib.sr3d_tv_admm.restype = ci
         lib.sr3d_batch.argtypes = [ctypes.POINTER(Problem), ci, ci, ctypes.POINTER(Stats), vp, sz, vp]
@@ -191,6 +212,12 @@ def workspace_bytes(op, problems):
     return int(load().sr3d_workspace_size(op, arr, len(problems)))
 
 
+def workspace_bytes_n(op, problem, count):
+    """sr3d_workspace_size for one problem with a count (frames of a
+    multi-frame op)."""
+    return int(load().sr3d_workspace_size(op, ctypes.byref(problem), int(count)))
+
+
 def _workspace(nbytes, device):
     import torch
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
@@ -249,6 +276,72 @@ def tikhonov_noalloc(y, psf, rate, lam, xbar=None, out=None, stream=None):
                                         dims_of(psf.shape), _ptr(xbar), float(lam), _ptr(x),
                                         _stream(stream)))
     return x
+
+
+def _frames(ys, shifts):
+    if len(ys) != len(shifts) or not 1 <= len(ys) <= MAX_FRAMES:
+        raise ValueError(f"1..{MAX_FRAMES} frames, one shift (t_m, t_n, t_s) each")
+    for y in ys:
+        _dev_f32(y, "frame")
+    ptrs = (ctypes.c_void_p * len(ys))(*[_ptr(y) for y in ys])
+    sh = (ctypes.c_int * (3 * len(ys)))(*[int(v) for t in shifts for v in t])
+    return ptrs, sh
+
+
+def tikhonov_mf(ys, shifts, psf, rate, lam, xbar=None, out=None, stream=None):
+    """Multi-frame Tikhonov: frames ys[f] (LR, device) observed after HR
+    shifts shifts[f] = (t_m, t_n, t_s); returns x (HR)."""
+    import torch
+    ptrs, sh = _frames(ys, shifts)
+    _dev_f32(psf, "psf")
+    if xbar is not None:
+        _dev_f32(xbar, "xbar")
+    hr = hr_shape(tuple(ys[0].shape), rate)
+    x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=ys[0].device)
+    p = _problem(hr, rate, psf)
+    ws = _workspace(workspace_bytes_n(OP_TIKHONOV_MF, p, len(ys)), ys[0].device)
+    _check(load().sr3d_tikhonov_mf(dims_of(hr), rate_of(rate), len(ys), ptrs, sh, _ptr(psf),
+                                   dims_of(psf.shape), _ptr(xbar), float(lam), _ptr(x), _ptr(ws),
+                                   ws.numel(), _stream(stream)))
+    return x
+
+
+def tv_admm_mf(ys, shifts, psf, rate, lam, mu, max_iter, tol=0.0, x0=None, flags=FP64_REDUCE,
+               out=None, stream=None):
+    """Algorithm 1 with the multi-frame data term. Returns (x, AdmmStats)."""
+    import torch
+    ptrs, sh = _frames(ys, shifts)
+    _dev_f32(psf, "psf")
+    if x0 is not None:
+        _dev_f32(x0, "x0")
+    hr = hr_shape(tuple(ys[0].shape), rate)
+    x = out if out is not None else torch.empty(hr, dtype=torch.float32, device=ys[0].device)
+    p = _problem(hr, rate, psf, lam, mu, tol, max_iter, y=ys[0], x=x, x0=x0)
+    ws = _workspace(workspace_bytes_n(OP_TV_ADMM_MF, p, len(ys)), ys[0].device)
+    st = Stats()
+    _check(load().sr3d_tv_admm_mf(ctypes.byref(p), len(ys), ptrs, sh, int(flags), ctypes.byref(st),
+                                  _ptr(ws), ws.numel(), _stream(stream)))
+    return x, _stats(st)
+
+
+def psf_fit(x, y, rate, radius, sigma0=(1.0, 1.0, 1.0), max_iter=50, tol=1e-6, stream=None):
+    """Gaussian PSF estimation (sr3d_psf_fit) from an HR reference x and the
+    LR volume y. radius and sigma0 are (m, n, s). Returns a dict with sigma
+    (m, n, s), gain, offset, objective, passes, converged."""
+    _dev_f32(x, "x")
+    _dev_f32(y, "y")
+    hr = tuple(x.shape)
+    p = Problem()
+    p.hr, p.rate = dims_of(hr), rate_of(rate)
+    ws = _workspace(workspace_bytes(OP_PSF_FIT, [p]), x.device)
+    res = PsfFitResult()
+    rad = (ctypes.c_int * 3)(*[int(r) for r in radius])
+    s0 = (ctypes.c_double * 3)(*[float(v) for v in sigma0])
+    _check(load().sr3d_psf_fit(dims_of(hr), rate_of(rate), _ptr(x), _ptr(y), ctypes.byref(rad),
+                               ctypes.byref(s0), int(max_iter), float(tol), ctypes.byref(res),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+    return {"sigma": tuple(res.sigma), "gain": res.gain, "offset": res.offset,
+            "objective": res.objective, "passes": res.passes, "converged": bool(res.converged)}
 
 
 @dataclass

@@ -199,3 +199,55 @@ def test_l1_data_host_argument_errors():
         "SR3D_ERR_WORKSPACE"
     arr = (sr3d.Problem * 1)(p)
     assert lib.sr3d_batch(arr, 1, sr3d.DATA_L1, None, None, 0, None) == -1
+
+
+def test_psf_fit_host_argument_errors():
+    lib = sr3d.load()
+    hr, rate = sr3d.Dims(32, 32, 32), sr3d.Rate(2, 2, 2)
+    rad = (ctypes.c_int * 3)(3, 3, 3)
+    s0 = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    res = sr3d.PsfFitResult()
+
+    def call(r=rad, s=s0, it=10, tol=1e-8, x=1, y=9, h=hr):
+        return sr3d.STATUS[lib.sr3d_psf_fit(h, rate, x, y, ctypes.byref(r), ctypes.byref(s), it,
+                                            tol, ctypes.byref(res), None, 0, None)]
+
+    assert call() == "SR3D_ERR_WORKSPACE"
+    assert call(r=(ctypes.c_int * 3)(3, -1, 3)) == "SR3D_ERR_INVALID_ARG"
+    assert call(s=(ctypes.c_double * 3)(1.0, 0.0, 1.0)) == "SR3D_ERR_INVALID_ARG"
+    assert call(it=0) == "SR3D_ERR_INVALID_ARG"
+    assert call(tol=-1.0) == "SR3D_ERR_INVALID_ARG"
+    assert call(x=None) == "SR3D_ERR_INVALID_ARG"
+    assert call(h=sr3d.Dims(2, 2, 2)) == "SR3D_ERR_INVALID_ARG"  # one LR voxel
+    p = sr3d.Problem()
+    p.hr, p.rate = hr, rate
+    assert lib.sr3d_workspace_size(sr3d.OP_PSF_FIT, ctypes.byref(p), 1) > 8 * 32 * 32 * 17
+
+
+def test_multi_frame_host_argument_errors():
+    lib = sr3d.load()
+    hr, rate, psfd = sr3d.Dims(32, 32, 32), sr3d.Rate(2, 2, 2), sr3d.Dims(5, 5, 5)
+    ptrs = (ctypes.c_void_p * 4)(1, 2, 3, 4)
+    sh = (ctypes.c_int * 12)(*range(12))
+
+    def tik(n=2, p=ptrs, s=sh, r=rate):
+        return sr3d.STATUS[lib.sr3d_tikhonov_mf(hr, r, n, p, s, 9, psfd, None, 1e-3, 17, None, 0,
+                                                None)]
+
+    assert tik() == "SR3D_ERR_WORKSPACE"
+    assert tik(n=0) == "SR3D_ERR_INVALID_ARG"
+    assert tik(n=5) == "SR3D_ERR_INVALID_ARG"
+    assert tik(s=None) == "SR3D_ERR_INVALID_ARG"
+    assert tik(p=(ctypes.c_void_p * 4)(1, None, 3, 4)) == "SR3D_ERR_INVALID_ARG"
+    assert tik(r=sr3d.Rate(3, 1, 1), n=1) == "SR3D_ERR_NOT_DIVISIBLE"
+    p = _prob()
+    assert sr3d.STATUS[lib.sr3d_tv_admm_mf(ctypes.byref(p), 2, ptrs, sh, 0, None, None, 0,
+                                           None)] == "SR3D_ERR_WORKSPACE"
+    for bad in (sr3d.REG_HAAR, sr3d.WARM_DUAL, sr3d.DATA_L1):
+        assert lib.sr3d_tv_admm_mf(ctypes.byref(p), 2, ptrs, sh, bad, None, None, 0, None) == -1
+    q = sr3d.Problem()
+    q.hr, q.rate, q.psf_dims = hr, rate, psfd
+    n1 = lib.sr3d_workspace_size(sr3d.OP_TIKHONOV_MF, ctypes.byref(q), 1)
+    n3 = lib.sr3d_workspace_size(sr3d.OP_TIKHONOV_MF, ctypes.byref(q), 3)
+    assert n3 > n1 > 0 and lib.sr3d_workspace_size(sr3d.OP_TIKHONOV_MF, ctypes.byref(q), 5) == 0
+    assert lib.sr3d_workspace_size(sr3d.OP_TV_ADMM_MF, ctypes.byref(q), 2) > n3
