@@ -176,6 +176,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="tv256: skip the batched and warm-started forms measured after the "
+                         "timed steps (the 'forms' record)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--workload", default="tv256",
@@ -312,6 +315,36 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(y.double().cpu().numpy(), psf.double().cpu().numpy(), wl, stats.iters)
 
+    # The forms, each against the plain GPU method on this GPU, measured after
+    # the timed steps (not part of `value`).
+    forms = None
+    if not (args.no_forms or args.separate_r2c or args.aniso or args.haar or args.data_l1 > 0):
+        del ws
+        torch.cuda.empty_cache()
+        b = bench_batch64(argparse.Namespace(steps=1, batch_only=False), emit=False)
+        torch.cuda.empty_cache()
+        w = bench_warm256(argparse.Namespace(pairs=args.pairs, train_steps=args.train_steps,
+                                             eval_volumes=args.eval_volumes), emit=False)
+        forms = {
+            "batch64": {"volumes": b["config"]["volumes"],
+                        "total_hr_voxels": b["config"]["total_hr_voxels"],
+                        "sequential_ms": b["sequential"]["ms_per_step"],
+                        "batched_ms": b["ms_per_step"],
+                        "speedup_vs_sequential": b["speedup_vs_sequential"],
+                        "same_iters_as_sequential": b["config"]["same_iters_as_sequential"],
+                        "max_rel_l2_vs_sequential": b["config"]["max_rel_l2_vs_sequential"]},
+            "warm256": {"volumes": len(w["runs"]), "target": "the plain solve's final residuals",
+                        "plain_ms": 1e3 * w["mean_s"]["plain"],
+                        "warm_ms": 1e3 * w["mean_s"]["cnn_x0"],
+                        "speedup_vs_plain": w["value"],
+                        "mean_iters_plain": w["mean_iters"]["plain"],
+                        "mean_iters_warm": w["mean_iters"]["cnn_x0"],
+                        "fallbacks": w["fallbacks"],
+                        "inference_ms": 1e3 * w["cnn_inference_256"]["s"],
+                        "inference_tflops": w["cnn_inference_256"]["tflops"],
+                        "train_s": w["config"]["train_s"]},
+        }
+
     out = {
         "metric": METRIC, "value": value, "unit": "HR voxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -333,6 +366,7 @@ def main():
                    "parallelism": "single_gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
@@ -366,7 +400,7 @@ def batch64_problems(torch, sr3d, phantom, dev, count=64, seed0=100):
     return probs
 
 
-def bench_batch64(args):
+def bench_batch64(args, emit=True):
     """Batched form: 64 uneven volumes solved (a) one after another with the
     plain single-volume solver and (b) together by sr3d_batch (HIP-graph
     replay), to the same tolerance; reports both rates and the speedup."""
@@ -437,7 +471,9 @@ def bench_batch64(args):
                        {"value": nh / (ms_seq / 1e3), "ms_per_step": ms_seq}),
         "speedup_vs_sequential": None if ms_seq is None else ms_seq / ms_bat,
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 PSF_WORKLOAD = dict(hr=(256, 256, 256), rate=(2, 2, 2), sigma=(1.8, 1.5, 1.1), radius=(6, 6, 6),
@@ -541,7 +577,7 @@ def bench_mf256(args):
 VARIANTS = ("plain", "tikhonov_x0", "cnn_x0", "tikhonov_x0_dual", "cnn_x0_dual")
 
 
-def bench_warm256(args):
+def bench_warm256(args, emit=True):
     """Learned warm start: pairs from 64^3 phantoms (batched plain ADMM), GPU
     training, then on 256^3 volumes like the headline workload: iterations and
     wall time to reach the plain run's final residuals from x0 = 0, from the
@@ -591,8 +627,12 @@ def bench_warm256(args):
             lambda: admm(sr3d.tikhonov(y, psf, rate, 1e-3), tp, td))
         xt = sr3d.tikhonov(y, psf, rate, 1e-3)
         _, t_inf = warmstart.timed(lambda: sr3d.cnn_forward(params, xt, ws=cws))
-        (_, stc), tc = warmstart.timed(
-            lambda: admm(warmstart.warm_start(params, y, psf, rate, ws=cws), tp, td))
+        # the accept-or-fall-back solve: Tikhonov, inference, the warm-started
+        # ADMM and, if it misses the target, plain ADMM; all of it timed
+        (_, wsol), tc = warmstart.timed(
+            lambda: warmstart.solve(params, y, psf, rate, wl["lam"], wl["mu"], wl["max_iter"],
+                                    tol=tp, tol_dual=td, out=x, workspace=ws, cnn_ws=cws))
+        stc = wsol.warm
         (_, sttd), ttd = warmstart.timed(
             lambda: admm(sr3d.tikhonov(y, psf, rate, 1e-3), tp, td, dual=True))
         (_, stcd), tcd = warmstart.timed(
@@ -604,7 +644,8 @@ def bench_warm256(args):
                      "plain": {"iters": stp.iters, "reached": stp.converged, "s": tpl},
                      "tikhonov_x0": {"iters": stt.iters, "reached": stt.converged, "s": tt},
                      "cnn_x0": {"iters": stc.iters, "reached": stc.converged, "s": tc,
-                                "inference_s": t_inf},
+                                "inference_s": t_inf, "used": wsol.used,
+                                "fallback_iters": None if wsol.plain is None else wsol.plain.iters},
                      "tikhonov_x0_dual": {"iters": sttd.iters, "reached": sttd.converged, "s": ttd},
                      "cnn_x0_dual": {"iters": stcd.iters, "reached": stcd.converged, "s": tcd}})
         print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
@@ -613,7 +654,8 @@ def bench_warm256(args):
     out = {
         "metric": "warm start: wall time to the plain solve's final residuals, 256^3 TV-ADMM",
         "value": mean("plain", lambda r: r["s"]) / mean("cnn_x0", lambda r: r["s"]),
-        "unit": "speedup (plain / CNN warm start, Tikhonov and inference included)",
+        "unit": "speedup (plain / CNN warm start; Tikhonov, inference and any fallback included)",
+        "fallbacks": int(sum(r["cnn_x0"]["used"] == "plain" for r in runs)),
         "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32 solver, bf16 CNN", "data": "synthetic",
         "config": {"workload": "warm256", "train_pairs": args.pairs, "train_steps": args.train_steps,
@@ -628,7 +670,9 @@ def bench_warm256(args):
         "reached": {k: int(sum(r[k]["reached"] for r in runs)) for k in VARIANTS},
         "runs": runs,
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

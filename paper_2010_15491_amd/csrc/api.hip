@@ -336,8 +336,17 @@ MfArgs make_mf(const Geometry &g, const float2 *lam, const float2 *yf, int nfram
                const int (*t)[3]) {
   MfArgs a{};
   a.Lam = lam; a.Yf = yf; a.nlspec = g.nlspec; a.F = nframes;
-  for (int f = 0; f < nframes; ++f)
+  for (int f = 0; f < nframes; ++f) {
     for (int c = 0; c < 3; ++c) a.t[f][c] = t[f][c];
+    // per-member roots of unity, in FP64 (member q = (c dc + b) dr + a)
+    for (int q = 0; q < g.D && q < 32; ++q) {
+      const int ia = q % g.dr, ib = (q / g.dr) % g.dc, ic = q / (g.dr * g.dc);
+      const double ph = 2.0 * M_PI * ((double)(((long)ia * t[f][0]) % g.dr) / g.dr +
+                                      (double)(((long)ib * t[f][1]) % g.dc) / g.dc +
+                                      (double)(((long)ic * t[f][2]) % g.ds) / g.ds);
+      a.r[f][q] = make_float2((float)cos(ph), (float)sin(ph));
+    }
+  }
   a.twm = twiddles(g.M); a.twn = twiddles(g.N); a.tws = twiddles(g.S);
   a.S = g.S; a.N = g.N; a.M = g.M; a.Mh = g.Mh;
   a.Sl = g.Sl; a.Nl = g.Nl; a.Ml = g.Ml; a.Mlh = g.Mlh;

@@ -11,7 +11,11 @@
 // solved in FP64 (complex Cholesky) by the thread that owns the group. In a
 // TV solve the zero-frequency member has A = 0; that group is solved by the
 // Schur complement of member 0, with the same Woodbury solve for the rest.
-// The phase factors come from the FFT twiddle tables: w = conj(tw_n[k t mod n]).
+// The phase of member k = (j_m + a M_l, j_n + b N_l, j_s + c S_l) splits into
+// a per-group factor exp(2 pi i (j_m t_m / M + j_n t_n / N + j_s t_s / S))
+// (from the FFT twiddle tables, w = conj(tw_n[k t mod n])) and a per-member
+// root of unity exp(2 pi i (a t_m / d_r + b t_n / d_c + c t_s / d_s)), the
+// same for every group (a host table).
 #include "sr3d_internal.h"
 
 namespace sr3d {
@@ -113,9 +117,15 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
         }
       }
     }
+    // per-group phase factor of each frame
+    float2 base[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+      base[f] = f < F ? fmul(fmul(phase(a.twm, a.M, jm, a.t[f][0]), phase(a.twn, a.N, jn, a.t[f][1])),
+                             phase(a.tws, a.S, js, a.t[f][2]))
+                      : make_float2(0.f, 0.f);
     zd lam[D], B[D];
     double A[D];
-    int km_[D], kn_[D], ks_[D];
     long idx[D];
     bool own[D];
     int ia = 0, ib = 0, ic = 0;
@@ -139,13 +149,11 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
 #pragma unroll
       for (int f = 0; f < FM; ++f) {
         if (f < F) {
-          const float2 ph = fmul(fmul(phase(a.twm, a.M, km, a.t[f][0]), phase(a.twn, a.N, kn, a.t[f][1])),
-                                 phase(a.tws, a.S, ks, a.t[f][2]));
+          const float2 ph = fmul(base[f], a.r[f][q]);
           b = zadd(b, zmul(zconj(zmul(zf(ph), lam[q])), Y[f]));
         }
       }
       B[q] = b;
-      km_[q] = km; kn_[q] = kn; ks_[q] = ks;
       idx[q] = id;
       own[q] = direct;
       if (++ia == a.dr) {
@@ -156,12 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
         }
       }
     }
-    auto v_of = [&](int f, int q) {
-      const float2 ph = fmul(fmul(phase(a.twm, a.M, km_[q], a.t[f][0]),
-                                  phase(a.twn, a.N, kn_[q], a.t[f][1])),
-                             phase(a.tws, a.S, ks_[q], a.t[f][2]));
-      return zmul(zf(ph), lam[q]);
-    };
+    auto v_of = [&](int f, int q) { return zmul(zf(fmul(base[f], a.r[f][q])), lam[q]); };
     // Woodbury over members q0 .. D-1 (A > 0 there): Q t = V^T A^-1 z.
     auto woodbury = [&](int q0, const zd *z, zd *out) {
       zd Q[FM][FM], t[FM];

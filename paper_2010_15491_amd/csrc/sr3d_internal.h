@@ -196,6 +196,8 @@ struct MfArgs {
   const float *gm, *gn, *gs;
   const float2 *twm, *twn, *tws;  // exp(-2 pi i k / n) for n = M, N, S
   int t[kMaxFrames][3];           // shifts (t_m, t_n, t_s) of the frames
+  float2 r[kMaxFrames][32];       // member phase exp(2 pi i (a t_m/d_r + b t_n/d_c + c t_s/d_s)),
+                                  // member q = (c d_c + b) d_r + a
   int F;
   int S, N, M, Mh, Sl, Nl, Ml, Mlh, dr, dc, ds, ml_eff;
   float cw, coefA;
