@@ -182,12 +182,14 @@ def main():
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without per-kernel HIP events (no roofline)")
     ap.add_argument("--workload", default="tv256",
-                    choices=["tv256", "batch64", "warm256", "psf256", "mf256"],
+                    choices=["tv256", "batch64", "warm256", "psf256", "mf256", "cnn256"],
                     help="tv256: the headline single-volume solve; batch64: 64 uneven volumes, "
                          "sequential single solves vs one batched solve; warm256: train the "
                          "warm-start CNN on 64^3 pairs, then plain vs warm-started solves at 256^3; "
                          "psf256: Gaussian PSF fit from a 256^3 reference and its 128^3 LR volume; "
-                         "mf256: multi-frame TV-ADMM, four 128^3 frames of HR-shifted copies")
+                         "mf256: multi-frame TV-ADMM, four 128^3 frames of HR-shifted copies; "
+                         "cnn256: warm-start CNN inference on a 256^3 volume (seeded random "
+                         "weights) and one 64^3 training gradient per step")
     ap.add_argument("--separate-r2c", action="store_true",
                     help="tv256: run the tiled stencil and the m-axis R2C as separate kernels "
                          "(SR3D_SEPARATE_R2C) instead of the fused stencil")
@@ -221,6 +223,8 @@ def main():
         return bench_psf256(args)
     if args.workload == "mf256":
         return bench_mf256(args)
+    if args.workload == "cnn256":
+        return bench_cnn256(args)
 
     import numpy as np
     import torch
@@ -478,6 +482,51 @@ def bench_batch64(args, emit=True):
 
 PSF_WORKLOAD = dict(hr=(256, 256, 256), rate=(2, 2, 2), sigma=(1.8, 1.5, 1.1), radius=(6, 6, 6),
                     gain=0.9, offset=0.05, noise=0.01, seed=1)
+
+
+def bench_cnn256(args):
+    """Warm-start CNN alone: one step = one inference x0 = x + f(x) on a 256^3
+    volume (standard normal input, network initialised from seed 7), then one
+    loss gradient on a 64^3 volume. Inference FLOPs count the useful
+    multiply-adds of the six layers (27 taps; 1->32, 4 x 32->32, 32->1)."""
+    import torch
+    from paper_2010_15491_amd import sr3d
+
+    sr3d.load()
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(7)
+    params = sr3d.cnn_init(7)
+    x = torch.randn((256, 256, 256), device=dev, generator=g)
+    ws = sr3d.CnnWorkspace(x.shape)
+    y = sr3d.cnn_forward(params, x, ws=ws)
+    x64 = torch.randn((64, 64, 64), device=dev, generator=g)
+    t64 = x64 + 0.01
+    ws64 = sr3d.CnnWorkspace(x64.shape)
+    for _ in range(max(args.warmup, 1)):
+        sr3d.cnn_forward(params, x, out=y, ws=ws)
+        sr3d.cnn_grad(params, x64, t64, ws=ws64)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_inf = t_grad = 0.0
+    for _ in range(args.steps):
+        ev[0].record()
+        sr3d.cnn_forward(params, x, out=y, ws=ws)
+        ev[1].record()
+        sr3d.cnn_grad(params, x64, t64, ws=ws64)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_inf += ev[0].elapsed_time(ev[1])
+        t_grad += ev[1].elapsed_time(ev[2])
+    ms_inf, ms_grad = t_inf / args.steps, t_grad / args.steps
+    flops = 2.0 * 256 ** 3 * 27 * (32 + 4 * 32 * 32 + 32)
+    out = {"metric": "warm-start CNN inference, 256^3", "value": flops / (ms_inf / 1e3) / 1e12,
+           "unit": "TFLOP/s (bf16 MFMA, useful FLOPs)", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_inf + ms_grad, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "cnn256", "inference_ms": ms_inf, "grad64_ms": ms_grad,
+                      "frac_of_bf16_peak": flops / (ms_inf / 1e3) / 2.5e15}}
+    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_psf256(args):

@@ -1689,7 +1689,7 @@ int sr3d_cnn_init(float *params, unsigned long long seed, hipStream_t st) {
 size_t sr3d_cnn_workspace_size(sr3d_dims d, int training) {
   long nv;
   if (check_cnn_dims(d, &nv)) return 0;
-  return cnn_layout(nv, training != 0, nullptr).bytes;
+  return cnn_layout(d.s, d.n, d.m, training != 0, nullptr).bytes;
 }
 
 int sr3d_cnn_forward(sr3d_dims d, const float *params, const float *x, float *y, void *ws,
@@ -1699,9 +1699,9 @@ int sr3d_cnn_forward(sr3d_dims d, const float *params, const float *x, float *y,
   if (rc) return rc;
   if (!params || !x || !y) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
   if (x == y) return fail(SR3D_ERR_INVALID_ARG, "y aliases x");
-  const CnnWs L0 = cnn_layout(nv, false, nullptr);
+  const CnnWs L0 = cnn_layout(d.s, d.n, d.m, false, nullptr);
   if (!ws || ws_bytes < L0.bytes) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
-  const CnnWs L = cnn_layout(nv, false, reinterpret_cast<char *>(ws));
+  const CnnWs L = cnn_layout(d.s, d.n, d.m, false, reinterpret_cast<char *>(ws));
   SR3D_TRY(cnn_forward(d.s, d.n, d.m, params, x, y, L, false, nullptr, nullptr, nullptr, st),
            "cnn forward");
   return SR3D_OK;
@@ -1713,9 +1713,9 @@ int sr3d_cnn_grad(sr3d_dims d, const float *params, const float *x, const float 
   int rc = check_cnn_dims(d, &nv);
   if (rc) return rc;
   if (!params || !x || !target || !grad || !loss) return fail(SR3D_ERR_INVALID_ARG, "NULL pointer");
-  const CnnWs L0 = cnn_layout(nv, true, nullptr);
+  const CnnWs L0 = cnn_layout(d.s, d.n, d.m, true, nullptr);
   if (!ws || ws_bytes < L0.bytes) return fail(SR3D_ERR_WORKSPACE, "workspace too small");
-  const CnnWs L = cnn_layout(nv, true, reinterpret_cast<char *>(ws));
+  const CnnWs L = cnn_layout(d.s, d.n, d.m, true, reinterpret_cast<char *>(ws));
   SR3D_TRY(cnn_grad(d.s, d.n, d.m, params, x, target, grad, loss, L, st), "cnn grad");
   return SR3D_OK;
 }

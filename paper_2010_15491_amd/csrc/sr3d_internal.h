@@ -389,7 +389,7 @@ struct CnnWs {
 };
 long cnn_param_count();
 long cnn_w_offset(int layer);
-CnnWs cnn_layout(long NV, bool training, char *base);
+CnnWs cnn_layout(int S, int N, int M, bool training, char *base);
 hipError_t cnn_init(float *params, uint64_t seed, hipStream_t st);
 hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int step, float lr, float b1,
                     float b2, float eps, hipStream_t st);

@@ -45,7 +45,7 @@ def cf(a):  # (s, n, m, C) -> (C, s, n, m)
     return np.moveaxis(a, -1, 0)
 
 
-SHAPES = [(16, 12, 24), (8, 8, 8), (5, 6, 7)]
+SHAPES = [(16, 12, 24), (8, 8, 8), (5, 6, 7), (9, 20, 72), (1, 2, 3)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
