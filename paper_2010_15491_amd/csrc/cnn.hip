@@ -133,8 +133,9 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 // have their own accumulators, selected at compile time by the phase of p
 // modulo 3, so each input voxel is read from HBM (1 + 2/8)(1 + 2/32) times per
 // chunk instead of once per tap. Weights and the plane live in LDS with the
-// 16-byte chunks of each 64-byte row XOR-swizzled by bits 1-2 of the row
-// index, so the 32 rows an MFMA operand gathers hit distinct banks. Each
+// 16-byte chunks of each 64-byte row XOR-swizzled by bits 2-3 of the row
+// index: the LDS serves 16 lanes of a 16-byte read per cycle, and 16
+// consecutive rows then cover its 64 banks once. Each
 // wavefront computes two 32-voxel rows; per tap and channel half one weight
 // operand serves both. The weights are MFMA's A operand and the voxels its B
 // operand, so D is [co][voxel] and a lane stores four consecutive channels
@@ -145,7 +146,7 @@ constexpr int kCvHalo = (kCvTN + 2) * kCvHW;
 constexpr int kCvQ = kCvHalo * 4;          // 16-byte chunks of a ring plane
 constexpr int kCvPf = (kCvQ + 255) / 256;  // chunks per thread
 
-__device__ __forceinline__ int cv_swz(int row, int c) { return row * 64 + ((c ^ ((row >> 1) & 3)) << 4); }
+__device__ __forceinline__ int cv_swz(int row, int c) { return row * 64 + ((c ^ ((row >> 2) & 3)) << 4); }
 
 struct Conv32Tile {
   int n0, m0, s0, s1;  // tile origin, output planes [s0, s1)
