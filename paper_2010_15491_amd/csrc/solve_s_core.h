@@ -193,39 +193,49 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   __syncthreads();
   fft_passes<S, T, TP, 0, 1>(lds, stw);
 
-  // Solve. Every LDS entry is read and written by one thread only.
+  // Solve. A group of up to DM members is spread over LANES = DM / 8
+  // consecutive lanes, 8 members each (lane sub holds members 8 sub .. 8 sub
+  // + 7), so every instance keeps the register footprint of the 8-member
+  // one. Every LDS entry is read and written by one lane only: a member's own
+  // entry and its mirror belong to it alone.
   // Group size: a compile-time constant in the EXACT instances (D = DM), so
   // the member loops unroll into straight-line code.
+  constexpr int LANES = DM / 8, DL = DM / LANES;
   const int D = EXACT ? DM : a.D;
   const float fd = (float)D;
+  const int sub = (int)threadIdx.x & (LANES - 1), gi = (int)threadIdx.x / LANES;
+  const int gbase = ((int)threadIdx.x & 63) - sub;  // lane of member 0's owner
+  constexpr int GT = kThreads / LANES;              // groups in flight per workgroup
+  // member 8 sub -> (a, b, c) counters along m, n, s
+  const int m0 = sub * DL, ia0 = m0 % a.dr, ib0 = (m0 / a.dr) % a.dc, ic0 = m0 / (a.dr * a.dc);
   Acc resid = 0;
   // Lambda of member q of slot i at Lu[q * gmax + i]; Y of slot i at Yu[i]
-  cgu64 *Lu = (cgu64 *)a.Lg + (long)u * D * a.gmax;
+  cgu64 *Lu = (cgu64 *)a.Lg + (long)u * D * a.gmax + (long)m0 * a.gmax;
   cgu64 *Yu = (cgu64 *)a.Yg + (long)u * a.gmax;
   // Lambda and Y of the next slot are loaded while the current one is solved.
-  float2 lnext[DM], ynext = make_float2(0.f, 0.f);
+  float2 lnext[DL], ynext = make_float2(0.f, 0.f);
   const int nc = ut.nc, gcount = a.Sl * 2 * nc;  // slots of this unit
-  if ((int)threadIdx.x < gcount) {
-    ynext = u64_f2(Yu[threadIdx.x]);
+  if (gi < gcount) {
+    ynext = u64_f2(Yu[gi]);
 #pragma unroll
-    for (int q = 0; q < DM; ++q)
-      if (q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + threadIdx.x]);
+    for (int q = 0; q < DL; ++q)
+      if (EXACT || m0 + q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + gi]);
   }
-  // slot -> (ci, r1) advanced incrementally: kThreads = dq * nc + dr
-  const int dq = kThreads / nc, dr = kThreads - dq * nc;
-  int sci = (int)threadIdx.x % nc, sr1 = (int)threadIdx.x / nc;
-  for (int slot = threadIdx.x; slot < gcount; slot += kThreads) {
+  // slot -> (ci, r1) advanced incrementally: GT = dq * nc + dr
+  const int dq = GT / nc, dr = GT - dq * nc;
+  int sci = gi % nc, sr1 = gi / nc;
+  for (int slot = gi; slot < gcount; slot += GT) {
     const int ci = sci;
-    float2 lcur[DM];
+    float2 lcur[DL];
 #pragma unroll
-    for (int q = 0; q < DM; ++q) lcur[q] = lnext[q];
+    for (int q = 0; q < DL; ++q) lcur[q] = lnext[q];
     const float2 Yj = ynext;
-    const int nslot = slot + kThreads;
+    const int nslot = slot + GT;
     if (nslot < gcount) {
       ynext = u64_f2(Yu[nslot]);
 #pragma unroll
-      for (int q = 0; q < DM; ++q)
-        if (q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
+      for (int q = 0; q < DL; ++q)
+        if (EXACT || m0 + q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
     }
     SlotGroup g;
     const bool ok = slot_group_at(a, ut.mj, ci, sr1, j0, j1, g);
@@ -235,18 +245,18 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
       sci -= nc;
       ++sr1;
     }
-    if (!ok) continue;
+    if (!ok) continue;  // the same for every lane of the group
     // Members: Lambda, B = conj(Lambda) Y + mu W, A = mu G, the LDS index of
     // the stored entry (li >= 0: the member itself, else -1-index of its
     // mirror) and, for a stored member whose -k is stored as well and belongs
     // to the partner group, the LDS index of -k (mi, else -1).
-    float2 B[DM];
-    float A[DM];
-    int li[DM], mi[DM];
-    int ia = 0, ib = 0, ic = 0;
+    float2 B[DL];
+    float A[DL];
+    int li[DL], mi[DL];
+    int ia = ia0, ib = ib0, ic = ic0;
 #pragma unroll
-    for (int q = 0; q < DM; ++q) {
-      if (q < D) {
+    for (int q = 0; q < DL; ++q) {
+      if (EXACT || m0 + q < D) {
         const int ks = g.js + ic * a.Sl;
         const int mp = ut.mpos[g.ci * a.dr + ia];
         const bool direct = (mp & (1 << 30)) == 0;
@@ -286,24 +296,29 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     if (!a.a_pos && g.js == 0 && g.jn == 0 && g.jm == 0) {
       // Zero-frequency group: member 0 is k = 0 with A = 0. Exact elimination
       // of (1/d) conj(L) L^T X + diag(A) X = B, in FP64.
-      const double l0r = lcur[0].x, l0i = lcur[0].y;
+      float2 L0 = lcur[0], B0 = B[0];
+      if (LANES > 1) {
+        L0 = make_float2(__shfl(L0.x, gbase), __shfl(L0.y, gbase));
+        B0 = make_float2(__shfl(B0.x, gbase), __shfl(B0.y, gbase));
+      }
+      const double l0r = L0.x, l0i = L0.y;
       const double l0n = l0r * l0r + l0i * l0i;
       if (l0n == 0.0) {
         a.ctrl->status = SR3D_ERR_SINGULAR;
         a.ctrl->done = 1;
 #pragma unroll
-        for (int q = 0; q < DM; ++q)
-          if (q < D) emit(q, make_float2(0.f, 0.f));
+        for (int q = 0; q < DL; ++q)
+          if (EXACT || m0 + q < D) emit(q, make_float2(0.f, 0.f));
         mean = make_float2(0.f, 0.f);
       } else {
-        const double br = B[0].x, bi = B[0].y;
+        const double br = B0.x, bi = B0.y;
         // s = sum_b L_b X_b = d B_0 / conj(L_0)
         const double sr = (double)D * (br * l0r - bi * l0i) / l0n;
         const double si = (double)D * (br * l0i + bi * l0r) / l0n;
         double accr = 0.0, acci = 0.0;
 #pragma unroll
-        for (int q = 1; q < DM; ++q) {
-          if (q < D) {
+        for (int q = 0; q < DL; ++q) {
+          if ((m0 + q > 0) && (EXACT || m0 + q < D)) {
             const double lr = lcur[q].x, lq = lcur[q].y;
             const double tr = (lr * sr + lq * si) / (double)D;
             const double ti = (lr * si - lq * sr) / (double)D;
@@ -314,9 +329,20 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
             acci += lr * xi + lq * xr;
           }
         }
+        if (LANES > 1) {  // lane totals in lane order
+          double tr = 0.0, ti = 0.0;
+#pragma unroll
+          for (int j = 0; j < LANES; ++j) {
+            tr += __shfl(accr, gbase + j);
+            ti += __shfl(acci, gbase + j);
+          }
+          accr = tr;
+          acci = ti;
+        }
         const double nr = sr - accr, ni = si - acci;
-        emit(0, make_float2((float)((nr * l0r + ni * l0i) / l0n) * a.scale,
-                            (float)((ni * l0r - nr * l0i) / l0n) * a.scale));
+        if (sub == 0)
+          emit(0, make_float2((float)((nr * l0r + ni * l0i) / l0n) * a.scale,
+                              (float)((ni * l0r - nr * l0i) / l0n) * a.scale));
         mean = make_float2((float)(sr / (double)D), (float)(si / (double)D));
       }
     } else {
@@ -324,14 +350,17 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
       // formula, with hardware reciprocals):
       //   X_a = [B_a (d + S_a^(-a)) - conj(L_a) S_b^(-a)] / [A_a (d + S_a)],
       //   S_a = sum_b |L_b|^2 / A_b,  S_b = sum_b L_b B_b / A_b.
-      // The group's mean (1/d) sum_b L_b X_b equals S_b / (d + S_a).
-      float inv[DM], pt[DM], preP[DM];
-      float2 qt[DM], preQ[DM];
+      // The leave-one-out sums are prefix + suffix sums over the members;
+      // across the lanes of a group, each lane adds the totals of the lanes
+      // before and after it. The group's mean (1/d) sum_b L_b X_b equals
+      // S_b / (d + S_a).
+      float inv[DL], pt[DL], preP[DL];
+      float2 qt[DL], preQ[DL];
       float sp = 0.f;
       float2 sq = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int q = 0; q < DM; ++q) {
-        if (q < D) {
+      for (int q = 0; q < DL; ++q) {
+        if (EXACT || m0 + q < D) {
           inv[q] = __builtin_amdgcn_rcpf(A[q]);
           const float2 l = lcur[q];
           const float2 lb = s_mul(l, B[q]);
@@ -344,16 +373,48 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
           sq.y += qt[q].y;
         }
       }
-      const float rS = __builtin_amdgcn_rcpf(fd + sp);
-      const float rSs = rS * a.scale;
-      float suP = 0.f;
-      float2 suQ = make_float2(0.f, 0.f);
+      // other lanes' totals: before this lane (pP, pQ), after it (fP, fQ), all (tP, tQ)
+      float pP = 0.f, fP = 0.f, tP = sp;
+      float2 pQ = make_float2(0.f, 0.f), fQ = pQ, tQ = sq;
+      if (LANES > 1) {
+        tP = 0.f;
+        tQ = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int q = DM - 1; q >= 0; --q) {
-        if (q < D) {
+        for (int j = 0; j < LANES; ++j) {
+          const float vP = __shfl(sp, gbase + j);
+          const float vx = __shfl(sq.x, gbase + j), vy = __shfl(sq.y, gbase + j);
+          tP += vP;
+          tQ.x += vx;
+          tQ.y += vy;
+          if (j < sub) {
+            pP += vP;
+            pQ.x += vx;
+            pQ.y += vy;
+          }
+        }
+#pragma unroll
+        for (int j = LANES - 1; j >= 0; --j) {
+          const float vP = __shfl(sp, gbase + j);
+          const float vx = __shfl(sq.x, gbase + j), vy = __shfl(sq.y, gbase + j);
+          if (j > sub) {
+            fP += vP;
+            fQ.x += vx;
+            fQ.y += vy;
+          }
+        }
+      }
+      const float rS = __builtin_amdgcn_rcpf(fd + tP);
+      const float rSs = rS * a.scale;
+      float suP = LANES > 1 ? fP : 0.f;
+      float2 suQ = LANES > 1 ? fQ : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int q = DL - 1; q >= 0; --q) {
+        if (EXACT || m0 + q < D) {
           const float2 l = lcur[q];
-          const float saL = preP[q] + suP;
-          const float2 sbL = make_float2(preQ[q].x + suQ.x, preQ[q].y + suQ.y);
+          const float pre = LANES > 1 ? pP + preP[q] : preP[q];
+          const float2 preq = LANES > 1 ? make_float2(pQ.x + preQ[q].x, pQ.y + preQ[q].y) : preQ[q];
+          const float saL = pre + suP;
+          const float2 sbL = make_float2(preq.x + suQ.x, preq.y + suQ.y);
           const float2 t = s_mul(s_conj(l), sbL);
           const float nd = fd + saL;
           const float rden = inv[q] * rSs;
@@ -363,10 +424,10 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
           suQ.y += qt[q].y;
         }
       }
-      mean = make_float2(sq.x * rS, sq.y * rS);
+      mean = make_float2(tQ.x * rS, tQ.y * rS);
     }
-    // Data residual of the new x at j (and, for a pair, at -j).
-    if (a.partial) {
+    // Data residual of the new x at j (and, for a pair, at -j); one lane per group.
+    if (a.partial && sub == 0) {
       const Acc rr = (Acc)Yj.x - (Acc)mean.x;
       const Acc ri = (Acc)Yj.y - (Acc)mean.y;
       resid += (g.selfc ? (Acc)1 : (Acc)2) * (rr * rr + ri * ri);
@@ -394,9 +455,10 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   }
 }
 
-// Two workgroups per CU (the LDS tile allows two) for the 8-member instances.
+// Two workgroups per CU (the LDS tile allows two); every instance holds 8
+// members per lane.
 template <int S, int DM, bool EXACT, typename Acc>
-__global__ __launch_bounds__(kThreads, (DM <= 8 ? 2 : 1)) void k_solve_s(const SolveSArgs *__restrict__ descs,
+__global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__restrict__ descs,
                                                       const int2 *__restrict__ items,
                                                       const float2 *__restrict__ tw) {
   int v = 0, u;
