@@ -9,10 +9,13 @@
 namespace sr3d {
 
 // Lines per workgroup: as many as fit two workgroups in a CU's 160 KB of LDS
-// (lines, twiddles, |sigma_s|^2 table and side tables), at most 64.
+// (lines, twiddles, |sigma_s|^2 table and side tables), at most 64, rounded
+// down to a multiple of 8 so that units of whole (2-column class x 4-row)
+// blocks fill the tile (32 of 32 lines at s = 256, d = 2^3, instead of 32 or
+// 36 of 37).
 constexpr int solve_tile(int S) {
   const int t = (81920 - 12 * S - 2048) / (8 * S);
-  return t > 64 ? 64 : t;
+  return t > 64 ? 64 : t / 8 * 8;
 }
 
 // ---------------------------------------------------------------------------
