@@ -293,13 +293,6 @@ void tv_choose_path(const Geometry &g, int flags, TvWs *L) {
   L->haar = (flags & SR3D_REG_HAAR) != 0;
   L->levels = haar_levels(flags);
   L->l1 = (flags & SR3D_DATA_L1) != 0;
-  if (L->l1) {
-    // The l1 data term runs the x-update on the natural spectrum (the fold
-    // kernel gives the LR spectrum of D H x) and the tiled stencil.
-    L->fused = false;
-    L->nbF = L->nbFold;
-    L->fsten = false;
-  }
   L->nbS = L->fsten ? L->nbSrow : L->nbStile;
   if (L->haar) {
     // The x-step is the Tikhonov solve (A = mu): the fused x-update with
@@ -323,6 +316,13 @@ SolveSArgs make_solve_args(const Geometry &g, const TvWs &L, const sr3d_problem 
   a.scale = (float)(1.0 / (double)g.NH);
   a.partial = L.partF; a.ctrl = L.ctrl; a.done = &L.ctrl->done;
   a.a_pos = L.haar ? 1 : 0;
+  if (L.l1) {
+    // l1 data term: mu -> mu / mu_data; the group means give the LR spectrum
+    // of D H x; its own test replaces the data-term partial sums
+    a.mu = p->mu / p->mu_data;
+    a.partial = nullptr;
+    a.dhx = L.l1sa;
+  }
   return a;
 }
 
@@ -616,29 +616,52 @@ hipError_t l1_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
 }
 
 // One iteration with the l1 data term: the x-step of Algorithm 1 with
-// y -> y' (its LR spectrum in yh) and mu -> mu / mu_data, whose fold also
-// leaves the LR spectrum of D H x; steps 5b/5c (tiled stencil, threshold
-// lam / mu); then on the LR grid D H x, steps 5b'/5c', the spectrum of the
-// next y', the data split's dual norms, and the stopping test over both
-// splits.
+// y -> y' (its LR spectrum in yh) and mu -> mu / mu_data, through the fused
+// x-update where the plan applies (else the fold on the natural spectrum),
+// either of which also leaves the LR spectrum of D H x; steps 5b/5c
+// (threshold lam / mu); then on the LR grid D H x, steps 5b'/5c', the
+// spectrum of the next y', the data split's dual norms, and the stopping test
+// over both splits.
 hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p, float *const nu[2],
                         int k, bool fp64, hipStream_t st) {
   const int *done = &L.ctrl->done;
   hipError_t e;
-  if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
-  const float mur = p->mu / p->mu_data;
-  FoldArgs fa = make_fold(g);
-  fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
-  fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
-  fa.cw = mur; fa.coefA = mur; fa.tv = 1;
-  fa.partial = nullptr; fa.ctrl = L.ctrl; fa.done = done; fa.dhx = L.l1sa;
-  if ((e = fold_solve(fa, fp64, st))) return e;
-  if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  if (L.fused) {
+    // The fused x-update, with y' (new every iteration) gathered into unit
+    // order; its group means leave the LR spectrum of D H x.
+    const int *kofp = L.tab, *posk = L.tab + g.Mh;
+    if ((e = solve_s_gather_y(make_solve_args(g, L, p), L.yh, g.Mlh, st))) return e;
+    if (L.fsten)
+      e = fft_n_forward(L.w, g.S, g.N, g.M, g.sp.pitch, done, st, nullptr);
+    else
+      e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st, nullptr);
+    if (e) return e;
+    prof_begin(kStSolveS, st);
+    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
+    prof_end(st);
+    if (e) return e;
+    if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
+      return e;
+  } else {
+    if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
+    const float mur = p->mu / p->mu_data;
+    FoldArgs fa = make_fold(g);
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
+    fa.cw = mur; fa.coefA = mur; fa.tv = 1;
+    fa.partial = nullptr; fa.ctrl = L.ctrl; fa.done = done; fa.dhx = L.l1sa;
+    if ((e = fold_solve(fa, fp64, st))) return e;
+    if ((e = fft3d_inverse(L.w2, p->x, g.S, g.N, g.M, 1.0f, done, st))) return e;
+  }
   AdmmStencilArgs sa{};
   sa.x = p->x; sa.nu_in = nu[(k - 1) & 1]; sa.nu_out = nu[k & 1]; sa.theta = L.theta;
   sa.S = g.S; sa.N = g.N; sa.M = g.M; sa.thr = p->lambda_tv / p->mu;
   sa.part = L.partS; sa.done = done; sa.aniso = L.aniso ? 1 : 0;
-  if ((e = admm_stencil(sa, true, fp64, st))) return e;
+  if (L.fsten)
+    e = admm_stencil_r2c(sa, L.w, L.tab, g.sp.pitch, fp64, st);
+  else
+    e = admm_stencil(sa, true, fp64, st);
+  if (e) return e;
   const int saved = t_prof.override_stage;
   t_prof.override_stage = kStL1Data;
   e = fft3d_inverse(L.l1sa, L.l1t, g.Sl, g.Nl, g.Ml, (float)(1.0 / (double)g.NL), done, st);

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
   const int nc = block_classes(mj, a.CB);
   if (slot >= a.Sl * 2 * nc || !slot_group(a, mj, nc, j0, j1, slot, g)) {
     Yg[i] = make_float2(0.f, 0.f);
-    for (int q = 0; q < a.D; ++q) Lg[((long)u * a.D + q) * a.gmax + slot] = make_float2(0.f, 0.f);
+    if (lam)
+      for (int q = 0; q < a.D; ++q) Lg[((long)u * a.D + q) * a.gmax + slot] = make_float2(0.f, 0.f);
     return;
   }
   float2 Yj;
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
     Yj = s_conj(yh[((long)ms * a.Nl + mn) * Mlh + (a.Ml - g.jm)]);
   }
   Yg[i] = Yj;
+  if (!lam) return;  // Y alone
   int ia = 0, ib = 0, ic = 0;
   for (int q = 0; q < a.D; ++q) {
     const int km = g.jm + ia * a.Ml, kn = g.jn + ib * a.Nl, ks = g.js + ic * a.Sl;
@@ -189,6 +191,10 @@ hipError_t solve_s_gather(const SolveSArgs &a, const float2 *lam, const float2 *
                      dim3(kThreads), 0, st, a, lam, yh, Mlh, const_cast<float2 *>(a.Lg),
                      const_cast<float2 *>(a.Yg));
   return hipGetLastError();
+}
+
+hipError_t solve_s_gather_y(const SolveSArgs &a, const float2 *yh, int Mlh, hipStream_t st) {
+  return solve_s_gather(a, nullptr, yh, Mlh, st);
 }
 
 }  // namespace sr3d

@@ -429,6 +429,16 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
       }
       mean = make_float2(tQ.x * rS, tQ.y * rS);
     }
+    // The LR spectrum of D H x at j and, where it is a stored entry too, at -j.
+    if (a.dhx && sub == 0) {
+      const int Mlh = a.Ml / 2 + 1;
+      gst2(a.dhx, ((uint32_t)(g.js * a.Nl + g.jn) * Mlh + g.jm) * 8u, mean);
+      const int jmp = g.jm ? a.Ml - g.jm : 0;
+      if (!g.selfc && jmp < Mlh) {
+        const int jsp = g.js ? a.Sl - g.js : 0, jnp = g.jn ? a.Nl - g.jn : 0;
+        gst2(a.dhx, ((uint32_t)(jsp * a.Nl + jnp) * Mlh + jmp) * 8u, s_conj(mean));
+      }
+    }
     // Data residual of the new x at j (and, for a pair, at -j); one lane per group.
     if (a.partial && sub == 0) {
       const Acc rr = (Acc)Yj.x - (Acc)mean.x;

@@ -238,6 +238,8 @@ struct SolveSArgs {
   int a_pos;          // A > 0 at every member (A = mu with gm = 1, gn = gs = 0: the Tikhonov
                       // x-step of the wavelet form); else A(0) = 0 and the zero-frequency
                       // group is eliminated exactly
+  float2 *dhx;        // optional: the LR half spectrum (S_l x N_l x (M_l/2 + 1)) of D H x
+                      // of the new x, written at every stored entry
 };
 // Unit structure. The LR columns (j_n, j_m) are split into n-groups (one
 // class {j_n, -j_n}, or the two self-conjugate classes {0} and {N_l/2}) and
@@ -259,6 +261,8 @@ struct SolveSPlan {
 };
 // Plans the fused x-update for an S x N x M volume at rates (dr, dc, ds).
 SolveSPlan solve_s_plan(int S, int N, int M, int dr, int dc, int ds);
+// Y alone in unit order (the l1 data term changes y' every iteration).
+hipError_t solve_s_gather_y(const SolveSArgs &a, const float2 *yh, int Mlh, hipStream_t st);
 hipError_t solve_s_gather(const SolveSArgs &a, const float2 *lam, const float2 *yh, int Mlh,
                           hipStream_t st);
 // descs: device array of per-volume arguments; items: (volume, unit) per

@@ -55,19 +55,27 @@ def l1_problem(shape, rate, sigma, seed, frac=0.1, amp=1.0):
     ((16, 16, 64), (1, 2, 2), 1.0, 1.0, 8, False),
 ])
 def test_l1data_fixed_iterations_match_oracle(shape, rate, sigma, mu_d, iters, aniso):
+    """Both x-update paths: the fused one (where its plan applies; with the
+    m-axis R2C fused into the stencil at m = 64) and the fold on the natural
+    spectrum (SR3D_UNFUSED)."""
     y, psf, _ = l1_problem(shape, rate, sigma, 80)
     flags = sr3d.FP64_REDUCE | sr3d.DATA_L1 | (sr3d.TV_ANISO if aniso else 0)
-    print(f"l1 data {shape} {rate} mu_d {mu_d} aniso {aniso}", flush=True)
-    x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM, MU, iters, flags=flags, mu_data=mu_d)
     ref = O.admm_l1data(y, psf, rate, LAM, MU, mu_d, iters, aniso=aniso)
-    assert st.iters == iters and not st.converged
-    err = close(host(x), ref.x)
-    print(f"  rel-L2 {err:.2e}, primal {st.primal_rel:.4e} vs {ref.primal_rel:.4e}, "
-          f"dual {st.dual_rel:.4e} vs {ref.dual_rel:.4e}")
-    assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
-    assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
-    assert np.isclose(st.objective, O.l1data_objective(host(x), y, psf, rate, LAM, aniso=aniso),
-                      rtol=1e-4)
+    xs = {}
+    for name, extra in (("default", 0), ("unfused", sr3d.UNFUSED)):
+        print(f"l1 data {shape} {rate} mu_d {mu_d} aniso {aniso} {name}", flush=True)
+        x, st = sr3d.tv_admm(dev(y), dev(psf), rate, LAM, MU, iters, flags=flags | extra,
+                             mu_data=mu_d)
+        assert st.iters == iters and not st.converged
+        err = close(host(x), ref.x)
+        print(f"  rel-L2 {err:.2e}, primal {st.primal_rel:.4e} vs {ref.primal_rel:.4e}, "
+              f"dual {st.dual_rel:.4e} vs {ref.dual_rel:.4e}")
+        assert np.isclose(st.primal_rel, ref.primal_rel, rtol=1e-3)
+        assert np.isclose(st.dual_rel, ref.dual_rel, rtol=1e-3)
+        assert np.isclose(st.objective,
+                          O.l1data_objective(host(x), y, psf, rate, LAM, aniso=aniso), rtol=1e-4)
+        xs[name] = host(x)
+    close(xs["default"], xs["unfused"], tol=1e-6, elem=1e-6)
 
 
 def test_l1data_warm_start_x0_fp32_reductions_and_graph():
