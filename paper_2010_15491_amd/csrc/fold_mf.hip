@@ -8,7 +8,7 @@
 //   B_a = sum_f conj(v_f,a) Y_f,j + c W_a.
 // Woodbury with the F x F matrix Q = d I + V^T A^-1 conj(V) gives
 //   Q t = V^T A^-1 B,   X_a = (B_a - sum_f conj(v_f,a) t_f) / A_a,
-// solved in FP64 (complex Cholesky) by the thread that owns the group. In a
+// solved in FP64 (complex Cholesky) by the lanes that own the group. In a
 // TV solve the zero-frequency member has A = 0; that group is solved by the
 // Schur complement of member 0, with the same Woodbury solve for the rest.
 // The phase of member k = (j_m + a M_l, j_n + b N_l, j_s + c S_l) splits into
@@ -84,15 +84,40 @@ __device__ __forceinline__ void chol_solve(zd (&Q)[FM][FM], zd (&b)[FM]) {
   }
 }
 
+// Sums over the LANES consecutive lanes of a group (xor butterfly: the same
+// bits in every lane of the group).
+template <int LANES>
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int LANES>
+__device__ __forceinline__ zd gsum(zd v) {
+  return {gsum<LANES>(v.x), gsum<LANES>(v.y)};
+}
+
+// One thread per group up to d = 8. The 16- and 32-member groups are spread
+// over LANES = d / 4 consecutive lanes, 4 members each (lane sub holds
+// members 4 sub .. 4 sub + 3): the F x F system and its right-hand side are
+// sums over members, reduced across the group's lanes, and every lane
+// factorises the same reduced matrix. (Splitting the 8-member groups as well
+// measured slower: each lane repeats the FP64 factorisation.) A workgroup
+// handles kThreads groups in LANES passes, so the partial sums stay one per
+// workgroup of kThreads groups.
 template <int D, int FM, typename Acc>
 __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
   if (a.done && *a.done) return;
+  constexpr int DL = D <= 8 ? D : 4, LANES = D / DL, GPP = kThreads / LANES;
   __shared__ Acc sh[kThreads / 64];
   const long ngroups = (long)a.Sl * a.Nl * a.ml_eff;
-  const long g = (long)blockIdx.x * kThreads + threadIdx.x;
   const int F = a.F;
+  const int sub = (int)threadIdx.x % LANES;
+  const int lbase = ((int)threadIdx.x & 63) - sub;  // lane of the group's first member
   Acc resid = 0;
-  if (g < ngroups) {
+  for (int pass = 0; pass < LANES; ++pass) {
+    const long g = (long)blockIdx.x * kThreads + pass * GPP + (long)threadIdx.x / LANES;
+    if (g >= ngroups) continue;  // the same for every lane of the group
     const int jm = (int)(g % a.ml_eff);
     const long r1 = g / a.ml_eff;
     const int jn = (int)(r1 % a.Nl);
@@ -124,13 +149,16 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
       base[f] = f < F ? fmul(fmul(phase(a.twm, a.M, jm, a.t[f][0]), phase(a.twn, a.N, jn, a.t[f][1])),
                              phase(a.tws, a.S, js, a.t[f][2]))
                       : make_float2(0.f, 0.f);
-    zd lam[D], B[D];
-    double A[D];
-    long idx[D];
-    bool own[D];
-    int ia = 0, ib = 0, ic = 0;
+    // this lane's members q = sub DL + i
+    const int q0l = sub * DL;
+    zd lam[DL], B[DL];
+    double A[DL];
+    long idx[DL];
+    bool own[DL];
+    int ia = q0l % a.dr, ib = (q0l / a.dr) % a.dc, ic = q0l / (a.dr * a.dc);
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
+    for (int i = 0; i < DL; ++i) {
+      const int q = q0l + i;
       const int km = jm + ia * a.Ml, kn = jn + ib * a.Nl, ks = js + ic * a.Sl;
       const bool direct = km < a.Mh;
       long id;
@@ -142,20 +170,20 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
         l.y = -l.y;
         w.y = -w.y;
       }
-      lam[q] = zf(l);
-      A[q] = a.tv ? (double)a.coefA * ((double)a.gs[ks] + (double)a.gn[kn] + (double)a.gm[km])
+      lam[i] = zf(l);
+      A[i] = a.tv ? (double)a.coefA * ((double)a.gs[ks] + (double)a.gn[kn] + (double)a.gm[km])
                   : (double)a.coefA;
       zd b = zscale(zf(w), (double)a.cw);
 #pragma unroll
       for (int f = 0; f < FM; ++f) {
         if (f < F) {
           const float2 ph = fmul(base[f], a.r[f][q]);
-          b = zadd(b, zmul(zconj(zmul(zf(ph), lam[q])), Y[f]));
+          b = zadd(b, zmul(zconj(zmul(zf(ph), lam[i])), Y[f]));
         }
       }
-      B[q] = b;
-      idx[q] = id;
-      own[q] = direct;
+      B[i] = b;
+      idx[i] = id;
+      own[i] = direct;
       if (++ia == a.dr) {
         ia = 0;
         if (++ib == a.dc) {
@@ -164,83 +192,100 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
         }
       }
     }
-    auto v_of = [&](int f, int q) { return zmul(zf(fmul(base[f], a.r[f][q])), lam[q]); };
-    // Woodbury over members q0 .. D-1 (A > 0 there): Q t = V^T A^-1 z.
-    auto woodbury = [&](int q0, const zd *z, zd *out) {
+    auto v_of = [&](int f, int i) { return zmul(zf(fmul(base[f], a.r[f][q0l + i])), lam[i]); };
+    // Woodbury over the members q >= qs (A > 0 there): Q t = V^T A^-1 z.
+    auto woodbury = [&](int qs, const zd *z, zd *out) {
       zd Q[FM][FM], t[FM];
 #pragma unroll
       for (int f = 0; f < FM; ++f) {
         t[f] = {0.0, 0.0};
 #pragma unroll
-        for (int h = 0; h < FM; ++h) Q[f][h] = {f == h ? (double)D : 0.0, 0.0};
+        for (int h = 0; h < FM; ++h) Q[f][h] = {(LANES == 1 && f == h) ? (double)D : 0.0, 0.0};
       }
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        if (q < q0) continue;
-        const double ia_ = 1.0 / A[q];
+      for (int i = 0; i < DL; ++i) {
+        if (q0l + i < qs) continue;
+        const double ia_ = 1.0 / A[i];
         zd v[FM];
 #pragma unroll
-        for (int f = 0; f < FM; ++f) v[f] = f < F ? v_of(f, q) : zd{0.0, 0.0};
+        for (int f = 0; f < FM; ++f) v[f] = f < F ? v_of(f, i) : zd{0.0, 0.0};
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
-          t[f] = zadd(t[f], zscale(zmul(v[f], z[q]), ia_));
+          t[f] = zadd(t[f], zscale(zmul(v[f], z[i]), ia_));
 #pragma unroll
           for (int h = f; h < FM; ++h) Q[f][h] = zadd(Q[f][h], zscale(zmul(v[f], zconj(v[h])), ia_));
         }
       }
+      if (LANES > 1) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+          t[f] = gsum<LANES>(t[f]);
+#pragma unroll
+          for (int h = f; h < FM; ++h) Q[f][h] = gsum<LANES>(Q[f][h]);
+          Q[f][f].x += (double)D;
+        }
+      }
       chol_solve<FM>(Q, t);
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        if (q < q0) continue;
-        zd s = z[q];
+      for (int i = 0; i < DL; ++i) {
+        if (q0l + i < qs) continue;
+        zd s = z[i];
 #pragma unroll
         for (int f = 0; f < FM; ++f)
-          if (f < F) s = zsub(s, zmul(zconj(v_of(f, q)), t[f]));
-        out[q] = zscale(s, 1.0 / A[q]);
+          if (f < F) s = zsub(s, zmul(zconj(v_of(f, i)), t[f]));
+        out[i] = zscale(s, 1.0 / A[i]);
       }
     };
-    zd X[D];
+    zd X[DL];
     if (a.tv && g == 0) {
-      // Zero-frequency group: member 0 has A = 0. Schur complement of member
-      // 0 with K_rr = diag(A_r) + (1/d) conj(V_r) V_r^T (Woodbury):
+      // Zero-frequency group: member 0 (lane 0 of the group) has A = 0. Schur
+      // complement of member 0 with K_rr = diag(A_r) + (1/d) conj(V_r) V_r^T
+      // (Woodbury):
       //   X_0 = (B_0 - K_0r K_rr^-1 B_r) / (k_00 - K_0r K_rr^-1 K_r0),
       //   X_r = K_rr^-1 (B_r - K_r0 X_0).
-      zd kr0[D], u1[D], u2[D];
+      zd lam0 = lam[0], B0 = B[0];
+      if (LANES > 1) {
+        lam0 = {__shfl(lam0.x, lbase), __shfl(lam0.y, lbase)};
+        B0 = {__shfl(B0.x, lbase), __shfl(B0.y, lbase)};
+      }
+      zd kr0[DL], u1[DL], u2[DL];
       double k00 = 0.0;
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        kr0[q] = {0.0, 0.0};
-        u1[q] = u2[q] = {0.0, 0.0};
-      }
+      for (int i = 0; i < DL; ++i) kr0[i] = u1[i] = u2[i] = {0.0, 0.0};
 #pragma unroll
       for (int f = 0; f < FM; ++f) {
         if (f >= F) continue;
-        const zd v0 = v_of(f, 0);
+        const zd v0 = zmul(zf(fmul(base[f], a.r[f][0])), lam0);
         k00 += (v0.x * v0.x + v0.y * v0.y) / (double)D;
 #pragma unroll
-        for (int q = 1; q < D; ++q) kr0[q] = zadd(kr0[q], zscale(zmul(zconj(v_of(f, q)), v0), 1.0 / D));
+        for (int i = 0; i < DL; ++i)
+          if (q0l + i >= 1) kr0[i] = zadd(kr0[i], zscale(zmul(zconj(v_of(f, i)), v0), 1.0 / D));
       }
       woodbury(1, B, u1);    // K_rr^-1 B_r
       woodbury(1, kr0, u2);  // K_rr^-1 K_r0
-      zd num = B[0], den = {k00, 0.0};
+      zd num = {0.0, 0.0}, den = {0.0, 0.0};
 #pragma unroll
-      for (int q = 1; q < D; ++q) {
+      for (int i = 0; i < DL; ++i) {
+        if (q0l + i < 1) continue;
         // K_0r = conj(K_r0)^T (K is Hermitian)
-        num = zsub(num, zmul(zconj(kr0[q]), u1[q]));
-        den = zsub(den, zmul(zconj(kr0[q]), u2[q]));
+        num = zadd(num, zmul(zconj(kr0[i]), u1[i]));
+        den = zadd(den, zmul(zconj(kr0[i]), u2[i]));
       }
+      num = zsub(B0, gsum<LANES>(num));
+      den = zsub(zd{k00, 0.0}, gsum<LANES>(den));
       const double dn = den.x * den.x + den.y * den.y;
       if (!(dn > 0.0)) {
         a.ctrl->status = SR3D_ERR_SINGULAR;
         a.ctrl->done = 1;
 #pragma unroll
-        for (int q = 0; q < D; ++q) X[q] = {0.0, 0.0};
+        for (int i = 0; i < DL; ++i) X[i] = {0.0, 0.0};
       } else {
-        X[0] = zscale(zmul(num, zconj(den)), 1.0 / dn);
-        zd z[D];
+        const zd x0 = zscale(zmul(num, zconj(den)), 1.0 / dn);
+        zd z[DL];
 #pragma unroll
-        for (int q = 0; q < D; ++q) z[q] = zsub(B[q], zmul(kr0[q], X[0]));
+        for (int i = 0; i < DL; ++i) z[i] = zsub(B[i], zmul(kr0[i], x0));
         woodbury(1, z, X);
+        if (sub == 0) X[0] = x0;
       }
     } else {
       woodbury(0, B, X);
@@ -254,14 +299,15 @@ __global__ __launch_bounds__(kThreads) void k_fold_solve_mf(MfArgs a) {
         if (f >= F) continue;
         zd m = {0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < D; ++q) m = zadd(m, zmul(v_of(f, q), X[q]));
+        for (int i = 0; i < DL; ++i) m = zadd(m, zmul(v_of(f, i), X[i]));
+        m = gsum<LANES>(m);
         const zd r = zsub(Y[f], zscale(m, 1.0 / D));
-        resid += wgt * (Acc)(r.x * r.x + r.y * r.y);
+        if (sub == 0) resid += wgt * (Acc)(r.x * r.x + r.y * r.y);
       }
     }
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-      if (own[q]) a.X[idx[q]] = make_float2((float)(X[q].x * a.scale), (float)(X[q].y * a.scale));
+    for (int i = 0; i < DL; ++i)
+      if (own[i]) a.X[idx[i]] = make_float2((float)(X[i].x * a.scale), (float)(X[i].y * a.scale));
   }
   if (a.partial) {
 #pragma unroll
