@@ -205,7 +205,7 @@ struct TvWs {
   // spectra of DHx, dv and e'; the weights of ||H^T D^T .||; partial sums
   bool l1;
   float *l1v, *l1e, *l1t, *l1yp, *l1dv, *l1w;
-  float2 *l1sa, *l1sb, *l1sc;
+  float2 *l1sa, *l1sy, *l1sb, *l1sc;  // spectra of DHx, y', dv, e
   void *partL, *partW;
   int nbL;
   // multi-frame data term (sr3d_tv_admm_mf): the frames' LR spectra and shifts
@@ -272,14 +272,16 @@ size_t tv_layout(const Geometry &g, char *base, TvWs *L) {
   L->l1 = false;
   L->nbL = l1_blocks(g.NL);
   L->l1v = c.take<float>(g.NL);
-  L->l1e = c.take<float>(g.NL);
   L->l1t = c.take<float>(g.NL);
-  L->l1yp = c.take<float>(g.NL);
-  L->l1dv = c.take<float>(g.NL);
+  // y', dv and e back to back, and their spectra: one stacked transform
+  L->l1yp = c.take<float>((size_t)3 * g.NL);
+  L->l1dv = L->l1yp + g.NL;
+  L->l1e = L->l1yp + 2 * (size_t)g.NL;
   L->l1w = c.take<float>(g.nlspec);
   L->l1sa = c.take<float2>(g.nlspec);
-  L->l1sb = c.take<float2>(g.nlspec);
-  L->l1sc = c.take<float2>(g.nlspec);
+  L->l1sy = c.take<float2>((size_t)3 * g.nlspec);
+  L->l1sb = L->l1sy + g.nlspec;
+  L->l1sc = L->l1sy + 2 * (size_t)g.nlspec;
   L->partL = c.take<double>((size_t)5 * L->nbL);
   L->partW = c.take<double>((size_t)2 * l1_blocks(g.nlspec));
   return c.off + 256;
@@ -612,7 +614,7 @@ hipError_t l1_setup(const Geometry &g, const TvWs &L, const sr3d_problem *p, flo
   if ((e = l1_update(t, p->y, L.l1v, L.l1e, L.l1yp, nullptr, g.NL, 1.0f / p->mu_data, true, nullptr,
                      false, nullptr, st)))
     return e;
-  return fft3d_forward(L.l1yp, L.yh, g.Sl, g.Nl, g.Ml, nullptr, st);
+  return fft3d_forward(L.l1yp, L.l1sy, g.Sl, g.Nl, g.Ml, nullptr, st);
 }
 
 // One iteration with the l1 data term: the x-step of Algorithm 1 with
@@ -630,7 +632,7 @@ hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
     // The fused x-update, with y' (new every iteration) gathered into unit
     // order; its group means leave the LR spectrum of D H x.
     const int *kofp = L.tab, *posk = L.tab + g.Mh;
-    if ((e = solve_s_gather_y(make_solve_args(g, L, p), L.yh, g.Mlh, st))) return e;
+    if ((e = solve_s_gather_y(make_solve_args(g, L, p), L.l1sy, g.Mlh, st))) return e;
     if (L.fsten)
       e = fft_n_forward(L.w, g.S, g.N, g.M, g.sp.pitch, done, st, nullptr);
     else
@@ -646,7 +648,7 @@ hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
     if ((e = fft3d_forward(L.theta, L.w, g.S, g.N, g.M, done, st))) return e;
     const float mur = p->mu / p->mu_data;
     FoldArgs fa = make_fold(g);
-    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.yh; fa.X = L.w2;
+    fa.W = L.w; fa.Lam = L.lam; fa.Yh = L.l1sy; fa.X = L.w2;
     fa.gm = L.g; fa.gn = L.g + g.M; fa.gs = L.g + g.M + g.N;
     fa.cw = mur; fa.coefA = mur; fa.tv = 1;
     fa.partial = nullptr; fa.ctrl = L.ctrl; fa.done = done; fa.dhx = L.l1sa;
@@ -671,9 +673,7 @@ hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
                   L.partL, fp64, done, st);
     prof_end(st);
   }
-  if (!e) e = fft3d_forward(L.l1yp, L.yh, g.Sl, g.Nl, g.Ml, done, st);
-  if (!e) e = fft3d_forward(L.l1dv, L.l1sb, g.Sl, g.Nl, g.Ml, done, st);
-  if (!e) e = fft3d_forward(L.l1e, L.l1sc, g.Sl, g.Nl, g.Ml, done, st);
+  if (!e) e = fft3d_forward_stack(L.l1yp, L.l1sy, 3, g.Sl, g.Nl, g.Ml, done, st);  // y', dv, e
   if (!e) {
     prof_begin(kStL1Data, st);
     e = l1_wnorm(L.l1sb, L.l1sc, L.l1w, g.nlspec, L.partW, fp64, done, st);

@@ -291,6 +291,22 @@ hipError_t fft3d_forward(const float *in, float2 *spec, int S, int N, int M, con
   return e;
 }
 
+hipError_t fft3d_forward_stack(const float *in, float2 *spec, int K, int S, int N, int M,
+                               const int *done, hipStream_t st) {
+  // m and n: the K volumes are K S planes of rows and columns; s: the columns
+  // of every volume, each volume's lines starting S N Mh further.
+  hipError_t e = run_kind(kFftR2cM, kStFftR2cM, in, nullptr, spec, K * S, N, M, 1.0f, done, st);
+  if (e == hipSuccess) e = run_kind(kFftFwdN, kStFftN, nullptr, nullptr, spec, K * S, N, M, 1.0f, done, st);
+  if (e == hipSuccess && S > 1) {
+    const long Mh = M / 2 + 1;
+    prof_begin(kStFftS, st);
+    e = launch_strided_v(spec, S, (long)K * N * Mh, (long)N * Mh, (long)S * N * Mh, (long)N * Mh,
+                         false, fft_variant(kFftFwdS, S), done, st);
+    prof_end(st);
+  }
+  return e;
+}
+
 hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                          const int *done, hipStream_t st) {
   hipError_t e = run_kind(kFftInvS, kStIfftS, nullptr, nullptr, spec, S, N, M, 1.0f, done, st);

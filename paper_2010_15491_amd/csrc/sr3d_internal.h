@@ -149,6 +149,10 @@ hipError_t fft3d_forward(const float *in, float2 *spec, int S, int N, int M,
                          const int *done, hipStream_t st);
 hipError_t fft3d_inverse(float2 *spec, float *out, int S, int N, int M, float scale,
                          const int *done, hipStream_t st);
+// The forward transform of K volumes stored back to back (inputs S N M
+// floats apart, spectra S N (M/2+1) apart), one launch per axis.
+hipError_t fft3d_forward_stack(const float *in, float2 *spec, int K, int S, int N, int M,
+                               const int *done, hipStream_t st);
 // The m and n passes alone (the s axis is left to the fused x-update), with
 // the m columns stored in the order kofp / posk and rows `pitch` apart.
 hipError_t fft2d_mn_forward(const float *in, float2 *spec, int S, int N, int M, const int *kofp,
