@@ -129,43 +129,70 @@ __global__ __launch_bounds__(kThreads) void k_l1_wnorm(const float2 *__restrict_
   }
 }
 
+// The 13 sums of the partial arrays (part k of an array at base + k n, n
+// entries) in one pass by the one workgroup of kRedThreads: grid-stride
+// loops, wavefront butterflies, then the wavefronts' totals in order.
+constexpr int kRedThreads = 256;
+
 template <typename Acc>
-__device__ __forceinline__ Acc sum_parts(const Acc *p, int n, Acc *sh) {
-  Acc s = 0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += p[i];
+__device__ __forceinline__ void sum_all_parts(const Acc *ps, int nbs, const Acc *pl, int nbl,
+                                              const Acc *pw, int nbw, Acc (&r)[13],
+                                              Acc (*sh)[13]) {
+  Acc v[13];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  for (int k = 0; k < 13; ++k) v[k] = 0;
+  for (int i = threadIdx.x; i < nbs; i += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] += ps[(long)k * nbs + i];
+  for (int i = threadIdx.x; i < nbl; i += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[6 + k] += pl[(long)k * nbl + i];
+  for (int i = threadIdx.x; i < nbw; i += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) v[11 + k] += pw[(long)k * nbw + i];
+#pragma unroll
+  for (int k = 0; k < 13; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 13; ++k) sh[wid][k] = v[k];
   __syncthreads();
-  if (lane == 0) sh[wid] = s;
-  __syncthreads();
-  Acc r = 0;
-  for (int i = 0; i < 16; ++i) r += sh[i];
-  __syncthreads();
-  return r;
+#pragma unroll
+  for (int k = 0; k < 13; ++k) {
+    Acc t = 0;
+#pragma unroll
+    for (int i = 0; i < kRedThreads / 64; ++i) t += sh[i][k];
+    r[k] = t;
+  }
 }
 
-// The stopping test over both splits (one workgroup of 1024 threads). TV
+// The stopping test over both splits (one workgroup). TV
 // split from the stencil sums (as in the plain solve), data split:
 //   primal = |DHx - y - v'| / max(|DHx|, |v'|, |y|),
 //   dual   = |H^T D^T (v' - v)| / |H^T D^T e'|  (mu_data cancels),
 // the reported primal and dual being the larger of the two splits'; the
 // objective is sum |DHx - y| + lam TV(x).
 template <typename Acc>
-__global__ __launch_bounds__(1024) void k_l1_reduce_test(Ctrl *c, const Acc *ps, int nbs,
+__global__ __launch_bounds__(kRedThreads) void k_l1_reduce_test(Ctrl *c, const Acc *ps, int nbs,
                                                          const Acc *pl, int nbl, const Acc *pw,
                                                          int nbw) {
   if (c->done) return;
-  __shared__ Acc sh[16];
-  Acc q[6], l[5], w[2];
-  for (int k = 0; k < 6; ++k) q[k] = sum_parts<Acc>(ps + (long)k * nbs, nbs, sh);
-  for (int k = 0; k < 5; ++k) l[k] = sum_parts<Acc>(pl + (long)k * nbl, nbl, sh);
-  for (int k = 0; k < 2; ++k) w[k] = sum_parts<Acc>(pw + (long)k * nbw, nbw, sh);
+  __shared__ Acc sh[kRedThreads / 64][13];
+  Acc r[13];
+  sum_all_parts<Acc>(ps, nbs, pl, nbl, pw, nbw, r, sh);
   if (threadIdx.x != 0) return;
+  Acc q[6], l[5], w[2];
   bool finite = true;
-  for (int k = 0; k < 6; ++k) finite = finite && isfinite(q[k]);
-  for (int k = 0; k < 5; ++k) finite = finite && isfinite(l[k]);
-  for (int k = 0; k < 2; ++k) finite = finite && isfinite(w[k]);
+#pragma unroll
+  for (int k = 0; k < 13; ++k) finite = finite && isfinite(r[k]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) q[k] = r[k];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) l[k] = r[6 + k];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) w[k] = r[11 + k];
   const Acc inf = (Acc)INFINITY;
   const Acc pden_tv = fmax(sqrt(q[1]), sqrt(q[2]));
   const Acc p_tv = pden_tv > 0 ? sqrt(q[0]) / pden_tv : inf;
@@ -236,10 +263,10 @@ hipError_t l1_reduce_test(Ctrl *c, const void *ps, int nbs, const void *pl, int 
                           int nbw, bool fp64, hipStream_t st) {
   prof_begin(kStReduce, st);
   if (fp64)
-    hipLaunchKernelGGL(k_l1_reduce_test<double>, dim3(1), dim3(1024), 0, st, c, (const double *)ps,
+    hipLaunchKernelGGL(k_l1_reduce_test<double>, dim3(1), dim3(kRedThreads), 0, st, c, (const double *)ps,
                        nbs, (const double *)pl, nbl, (const double *)pw, nbw);
   else
-    hipLaunchKernelGGL(k_l1_reduce_test<float>, dim3(1), dim3(1024), 0, st, c, (const float *)ps,
+    hipLaunchKernelGGL(k_l1_reduce_test<float>, dim3(1), dim3(kRedThreads), 0, st, c, (const float *)ps,
                        nbs, (const float *)pl, nbl, (const float *)pw, nbw);
   const hipError_t e = hipGetLastError();
   prof_end(st);
