@@ -1144,8 +1144,10 @@ int run_batch(const sr3d_problem *p, int count, int flags, sr3d_stats *stats, vo
     const int *kofp = L.fused ? L.tab : nullptr, *posk = L.fused ? L.tab + G.Mh : nullptr;
     float2 *xs = L.fused ? L.w : L.w2;  // spectrum of the x-update
     const long P = L.fused ? G.sp.pitch : Mh;  // spectrum row pitch
-    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P};
-    c2r[v] = RowDesc{nullptr, xs, p[v].x, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P};
+    r2c[v] = RowDesc{L.theta, L.w, nullptr, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P,
+                     RedArgs{}};
+    c2r[v] = RowDesc{nullptr, xs, p[v].x, (long)G.S * G.N, 1.0f, done, kofp, posk, (int)P,
+                     RedArgs{}};
     fn[v] = make_strided_desc(L.w, (long)G.S * P, P, (long)G.N * P, P, done, Mh);
     in_[v] = make_strided_desc(xs, (long)G.S * P, P, (long)G.N * P, P, done, Mh);
     fs[v] = make_strided_desc(L.w, (long)G.N * Mh, (long)G.N * Mh, 0, (long)G.N * Mh, done);

@@ -811,8 +811,6 @@ hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int step, floa
 hipError_t cnn_forward(int S, int N, int M, const float *params, const float *x, float *y,
                        const CnnWs &L, bool training, const float *target, float *gout,
                        float *lpart, hipStream_t st) {
-  const long NV = (long)S * N * M;
-  const unsigned vb = (unsigned)((NV + 255) / 256);
   hipLaunchKernelGGL(k_params_bf16, dim3((unsigned)((kCnnParams + 255) / 256)), dim3(256), 0, st,
                      params, L.wbf, (long)kCnnParams);
   int SC;

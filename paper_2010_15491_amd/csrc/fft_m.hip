@@ -332,7 +332,7 @@ hipError_t launch_c2r_m_v(const float2 *in, float *out, long nrows, int M, float
     return hipGetLastError();
   }
   if (M % 2) kofp = posk = nullptr;
-  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done, kofp, posk, pitch};
+  RowDesc d{nullptr, const_cast<float2 *>(in), out, nrows, scale, done, kofp, posk, pitch, RedArgs{}};
   return launch_rows(d, M, true, v, st);
 }
 
