@@ -139,6 +139,9 @@ struct Geometry {
   SolveSPlan sp;  // fused x-update plan (TV)
 };
 
+// Rates 2 x 2 x 2: the fused x-update has an instance specialised for them.
+static bool rates_222(const Geometry &g) { return g.dr == 2 && g.dc == 2 && g.ds == 2; }
+
 int check_geometry(sr3d_dims hr, sr3d_rate rate, const sr3d_dims *psf, Geometry *g) {
   if (hr.m < 1 || hr.n < 1 || hr.s < 1) return fail(SR3D_ERR_INVALID_ARG, "HR dimensions must be >= 1");
   if (rate.dr < 1 || rate.dc < 1 || rate.ds < 1) return fail(SR3D_ERR_INVALID_ARG, "rates must be >= 1");
@@ -563,7 +566,7 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
                               carry && merged ? &red : nullptr)))
       return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -639,7 +642,7 @@ hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
       e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st, nullptr);
     if (e) return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -710,7 +713,7 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
                            carry && merged ? &red : nullptr);
     if (e) return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -948,8 +951,10 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
   }
   for (int v = 0; v < n; ++v) {
     if (fused[v]) {
-      // variant: member bound, +1 for the instance with the group size fixed
-      auto &gr = group(8, g[v].S, 2 * g[v].sp.dm + (g[v].D == g[v].sp.dm ? 1 : 0));
+      // variant: 4 x member bound, +1 for the instance with the group size
+      // fixed, +2 for rates 2 x 2 x 2
+      auto &gr = group(8, g[v].S,
+                       4 * g[v].sp.dm + (g[v].D == g[v].sp.dm ? 1 : 0) + (rates_222(g[v]) ? 2 : 0));
       for (int t = 0; t < g[v].sp.units; ++t) gr.items.push_back(make_int2(v, t));
       continue;
     }
@@ -1056,9 +1061,9 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
   for (auto &gr : plan.groups) {
     if (gr.kind != 8) continue;
     prof_begin(kStSolveS, st);
-    const int dm = gr.variant / 2;
-    e = solve_s(gr.key, dm, (gr.variant & 1) ? dm : -1, H.solve, items_of(gr),
-                (int)gr.items.size(), fp64, st);
+    const int dm = gr.variant / 4;
+    e = solve_s(gr.key, dm, (gr.variant & 1) ? dm : -1, (gr.variant & 2) != 0, H.solve,
+                items_of(gr), (int)gr.items.size(), fp64, st);
     prof_end(st);
     if (e) return e;
   }

@@ -115,7 +115,7 @@ struct UnitTabs {
   float gnv[64];    // (ji, b): |sigma_n(k_n)|^2
 };
 
-template <int S, int DM, bool EXACT, typename Acc>
+template <int S, int DM, bool EXACT, bool G2, typename Acc>
 __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
                                              const float2 *__restrict__ tw, float2 *lds,
                                              float2 *stw, float *sgs, UnitTabs &ut, Acc *red) {
@@ -210,19 +210,25 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   const int gbase = ((int)threadIdx.x & 63) - sub;  // lane of member 0's owner
   constexpr int GT = kThreads / LANES;              // groups in flight per workgroup
   // member 8 sub -> (a, b, c) counters along m, n, s
-  const int m0 = sub * DL, ia0 = m0 % a.dr, ib0 = (m0 / a.dr) % a.dc, ic0 = m0 / (a.dr * a.dc);
+  // Rates along m and n: compile-time constants in the instance for
+  // d = 2 x 2 x 2, where every member's table indices then fold away.
+  const int GDR = G2 ? 2 : a.dr, GDC = G2 ? 2 : a.dc;
+  const int m0 = sub * DL, ia0 = m0 % GDR, ib0 = (m0 / GDR) % GDC, ic0 = m0 / (GDR * GDC);
   Acc resid = 0;
-  // Lambda of member q of slot i at Lu[q * gmax + i]; Y of slot i at Yu[i]
-  cgu64 *Lu = (cgu64 *)a.Lg + (long)u * D * a.gmax + (long)m0 * a.gmax;
-  cgu64 *Yu = (cgu64 *)a.Yg + (long)u * a.gmax;
+  // Lambda of member q of slot i at Lu + (q gmax + i) 8 bytes, Y of slot i at
+  // Yu + 8 i: 32-bit byte offsets from the unit's bases (at most
+  // 32 members x 2^16 slots x 8 bytes).
+  const char *Lu = (const char *)a.Lg + (size_t)u * D * a.gmax * 8;
+  const char *Yu = (const char *)a.Yg + (size_t)u * a.gmax * 8;
+  const uint32_t gstr = (uint32_t)a.gmax * 8u, lo0 = (uint32_t)m0 * gstr;
   // Lambda and Y of the next slot are loaded while the current one is solved.
   float2 lnext[DL], ynext = make_float2(0.f, 0.f);
   const int nc = ut.nc, gcount = a.Sl * 2 * nc;  // slots of this unit
   if (gi < gcount) {
-    ynext = u64_f2(Yu[gi]);
+    ynext = gld2(Yu, (uint32_t)gi * 8u);
 #pragma unroll
     for (int q = 0; q < DL; ++q)
-      if (EXACT || m0 + q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + gi]);
+      if (EXACT || m0 + q < D) lnext[q] = gld2(Lu, lo0 + q * gstr + (uint32_t)gi * 8u);
   }
   // slot -> (ci, r1) advanced incrementally: GT = dq * nc + dr
   const int dq = GT / nc, dr = GT - dq * nc;
@@ -235,10 +241,10 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     const float2 Yj = ynext;
     const int nslot = slot + GT;
     if (nslot < gcount) {
-      ynext = u64_f2(Yu[nslot]);
+      ynext = gld2(Yu, (uint32_t)nslot * 8u);
 #pragma unroll
       for (int q = 0; q < DL; ++q)
-        if (EXACT || m0 + q < D) lnext[q] = u64_f2(Lu[(long)q * a.gmax + nslot]);
+        if (EXACT || m0 + q < D) lnext[q] = gld2(Lu, lo0 + q * gstr + (uint32_t)nslot * 8u);
     }
     SlotGroup g;
     const bool ok = slot_group_at(a, ut.mj, ci, sr1, j0, j1, g);
@@ -261,25 +267,25 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
     for (int q = 0; q < DL; ++q) {
       if (EXACT || m0 + q < D) {
         const int ks = g.js + ic * a.Sl;
-        const int mp = ut.mpos[g.ci * a.dr + ia];
+        const int mp = ut.mpos[g.ci * GDR + ia];
         const bool direct = (mp & (1 << 30)) == 0;
-        const int nrow = g.ji * a.dc + ib;
+        const int nrow = g.ji * GDC + ib;
         const int rs = ks == 0 ? 0 : S - ks;
         const int mirror = rs * TP + ut.rowm[nrow] * cnt + (mp & ~(1 << 30));
-        const int idx = direct ? ks * TP + ut.rowd[nrow] * cnt + mp : mirror;
+        const int idx = direct ? ks * TP + nrow * cnt + mp : mirror;
         float2 w = lds[idx];
         if (!direct) w.y = -w.y;
         const float2 l = lcur[q];
-        const float Aq = a.mu * (sgs[ks] + ut.gnv[nrow] + ut.gmv[g.ci * a.dr + ia]);
+        const float Aq = a.mu * (sgs[ks] + ut.gnv[nrow] + ut.gmv[g.ci * GDR + ia]);
         const float2 cb = s_mul(s_conj(l), Yj);
         B[q] = make_float2(cb.x + a.mu * w.x, cb.y + a.mu * w.y);
         A[q] = Aq;
         li[q] = direct ? idx : -1 - idx;
         const int km = g.jm + ia * a.Ml;
         mi[q] = (direct && !g.selfc && (km == 0 || 2 * km == a.M)) ? mirror : -1;
-        if (++ia == a.dr) {
+        if (++ia == GDR) {
           ia = 0;
-          if (++ib == a.dc) {
+          if (++ib == GDC) {
             ib = 0;
             ++ic;
           }
@@ -469,8 +475,8 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
 }
 
 // Two workgroups per CU (the LDS tile allows two); every instance holds 8
-// members per lane.
-template <int S, int DM, bool EXACT, typename Acc>
+// members per lane. G2: every volume of the launch has rates 2 x 2 x 2.
+template <int S, int DM, bool EXACT, bool G2, typename Acc>
 __global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__restrict__ descs,
                                                       const int2 *__restrict__ items,
                                                       const float2 *__restrict__ tw) {
@@ -490,39 +496,47 @@ __global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__res
   __shared__ float sgs[S];
   __shared__ UnitTabs ut;
   __shared__ Acc red[kThreads / 64];
-  solve_s_body<S, DM, EXACT, Acc>(a, u, tw, lds, stw, sgs, ut, red);
+  solve_s_body<S, DM, EXACT, G2, Acc>(a, u, tw, lds, stw, sgs, ut, red);
 }
 
 template <int S, int DM, typename Acc>
-static void launch_solve_s_dm(bool exact, const SolveSArgs *descs, const int2 *items, int nwg,
-                              hipStream_t st) {
+static void launch_solve_s_dm(bool exact, bool g2, const SolveSArgs *descs, const int2 *items,
+                              int nwg, hipStream_t st) {
   const float2 *tw = twiddles(S);
+  if constexpr (DM == 8) {
+    if (exact && g2) {
+      hipLaunchKernelGGL((k_solve_s<S, DM, true, true, Acc>), dim3(nwg), dim3(kThreads), 0, st,
+                         descs, items, tw);
+      return;
+    }
+  }
   if (exact)
-    hipLaunchKernelGGL((k_solve_s<S, DM, true, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs,
-                       items, tw);
+    hipLaunchKernelGGL((k_solve_s<S, DM, true, false, Acc>), dim3(nwg), dim3(kThreads), 0, st,
+                       descs, items, tw);
   else
-    hipLaunchKernelGGL((k_solve_s<S, DM, false, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs,
-                       items, tw);
+    hipLaunchKernelGGL((k_solve_s<S, DM, false, false, Acc>), dim3(nwg), dim3(kThreads), 0, st,
+                       descs, items, tw);
 }
 
 // dm: member bound of the plan; d: the group size (the instance with
-// D = dm fixed at compile time runs when d == dm).
+// D = dm fixed at compile time runs when d == dm); g2: every volume has
+// rates 2 x 2 x 2.
 template <int S, typename Acc>
-static void launch_solve_s_t(int dm, int d, const SolveSArgs *descs, const int2 *items, int nwg,
-                             hipStream_t st) {
-  if (dm <= 8) launch_solve_s_dm<S, 8, Acc>(d == 8, descs, items, nwg, st);
-  else if (dm <= 16) launch_solve_s_dm<S, 16, Acc>(d == 16, descs, items, nwg, st);
-  else launch_solve_s_dm<S, 32, Acc>(d == 32, descs, items, nwg, st);
+static void launch_solve_s_t(int dm, int d, bool g2, const SolveSArgs *descs, const int2 *items,
+                             int nwg, hipStream_t st) {
+  if (dm <= 8) launch_solve_s_dm<S, 8, Acc>(d == 8, g2, descs, items, nwg, st);
+  else if (dm <= 16) launch_solve_s_dm<S, 16, Acc>(d == 16, false, descs, items, nwg, st);
+  else launch_solve_s_dm<S, 32, Acc>(d == 32, false, descs, items, nwg, st);
 }
 
 // One launcher per s-length, defined in the instantiating translation units.
-#define SR3D_SOLVE_S_LAUNCHER(L)                                                           \
-  void solve_s_launch_##L(int dm, int d, const SolveSArgs *descs, const int2 *items, int nwg, \
-                          bool fp64, hipStream_t st)
+#define SR3D_SOLVE_S_LAUNCHER(L)                                                     \
+  void solve_s_launch_##L(int dm, int d, bool g2, const SolveSArgs *descs,             \
+                          const int2 *items, int nwg, bool fp64, hipStream_t st)
 #define SR3D_SOLVE_S_DEFINE(L)                                                    \
   SR3D_SOLVE_S_LAUNCHER(L) {                                                      \
-    if (fp64) launch_solve_s_t<L, double>(dm, d, descs, items, nwg, st);          \
-    else launch_solve_s_t<L, float>(dm, d, descs, items, nwg, st);                \
+    if (fp64) launch_solve_s_t<L, double>(dm, d, g2, descs, items, nwg, st);      \
+    else launch_solve_s_t<L, float>(dm, d, g2, descs, items, nwg, st);            \
   }
 #define SR3D_SOLVE_S_LENGTHS(X) \
   X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)

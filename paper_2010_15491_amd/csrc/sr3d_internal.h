@@ -271,8 +271,9 @@ hipError_t solve_s_gather(const SolveSArgs &a, const float2 *lam, const float2 *
                           hipStream_t st);
 // descs: device array of per-volume arguments; items: (volume, unit) per
 // workgroup, or null for one volume (descs[0]) with `units` workgroups.
-hipError_t solve_s(int S, int dm, int d, const SolveSArgs *descs, const int2 *items, int nwg,
-                   bool fp64, hipStream_t st);
+// g2: every volume of the launch has rates 2 x 2 x 2 (a specialised instance).
+hipError_t solve_s(int S, int dm, int d, bool g2, const SolveSArgs *descs, const int2 *items,
+                   int nwg, bool fp64, hipStream_t st);
 
 // Fused difference / shrink / dual / Theta pass (Algorithm 1 steps 5b, 5c and
 // the Theta of the next 5a). State nu = L x + d_prev holds (u, d):
