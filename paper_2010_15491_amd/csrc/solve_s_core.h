@@ -43,6 +43,14 @@ __device__ __forceinline__ float2 gld2(const void *b, uint32_t off) {
 __device__ __forceinline__ void gst2(void *b, uint32_t off, float2 v) {
   *(gu64 *)((__attribute__((address_space(1))) char *)b + off) = f2_u64(v);
 }
+// two complex values (16 bytes) at byte offset `off`
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 gld4(const void *b, uint32_t off) {
+  return *(__attribute__((address_space(1))) const f32x4 *)((__attribute__((address_space(1))) const char *)b + off);
+}
+__device__ __forceinline__ void gst4(void *b, uint32_t off, f32x4 v) {
+  *(__attribute__((address_space(1))) f32x4 *)((__attribute__((address_space(1))) char *)b + off) = v;
+}
 
 __device__ __forceinline__ float2 s_mul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -176,6 +184,32 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   constexpr int NE = (S * T + kThreads - 1) / kThreads;
   constexpr int NH = (NE + 1) / 2;  // loads in flight per thread: half the tile
   const uint32_t pl = (uint32_t)plane;
+  // Where every row run of the unit has an even length and starts at an even
+  // column, lines 2i and 2i + 1 are adjacent columns of one row: each thread
+  // then moves pairs of them (16 bytes) with half the instructions.
+  const bool pairs = ((cnt | p0 | a.P) & 1) == 0;
+  constexpr int NP = (S * T / 2 + kThreads - 1) / kThreads;
+  constexpr int NPH = (NP + 1) / 2;
+  if (pairs) {
+#pragma unroll
+    for (int h = 0; h < NP; h += NPH) {
+      f32x4 v[NPH];
+#pragma unroll
+      for (int k = 0; k < NPH; ++k) {
+        const int w2 = threadIdx.x + (h + k) * kThreads;
+        const int s = w2 / (T / 2), line = 2 * (w2 - s * (T / 2));
+        const int off = (h + k < NP && w2 < S * T / 2) ? ut.loff[line] : -1;
+        const f32x4 x =
+            gld4(a.W, ((uint32_t)(off >= 0 ? s : 0) * pl + (uint32_t)(off >= 0 ? off : 0)) * 8u);
+        v[k] = off >= 0 ? x : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int k = 0; k < NPH; ++k) {
+        const int w2 = threadIdx.x + (h + k) * kThreads;
+        if (h + k < NP && w2 < S * T / 2) reinterpret_cast<f32x4 *>(lds)[w2] = v[k];
+      }
+    }
+  } else
 #pragma unroll
   for (int h = 0; h < NE; h += NH) {
     float2 v[NH];
@@ -458,6 +492,18 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   // phase (an empty asm hides that this is the same thread index).
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
+  if (pairs) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int w2 = tid + k * kThreads;
+      const int s = w2 / (T / 2), line = 2 * (w2 - s * (T / 2));
+      const int off = (w2 < S * T / 2) ? ut.loff[line] : -1;
+      if (off >= 0) {
+        const f32x4 v = reinterpret_cast<const f32x4 *>(lds)[w2];
+        gst4(a.W, ((uint32_t)s * pl + (uint32_t)off) * 8u, f32x4{v.x, -v.y, v.z, -v.w});
+      }
+    }
+  } else
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
     const int w = tid + k * kThreads;
@@ -491,7 +537,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__res
   const SolveSArgs a = descs[v];
   if (a.done && *a.done) return;
   constexpr int T = solve_tile(S);
-  __shared__ float2 lds[S * T + 1];  // + a spare entry for stores without a target
+  __shared__ __align__(16) float2 lds[S * T + 1];  // + a spare entry for stores without a target
   __shared__ float2 stw[S];
   __shared__ float sgs[S];
   __shared__ UnitTabs ut;
