@@ -391,6 +391,9 @@ FUSE_CASES = [
     ((384, 8, 8), (2, 2, 4)),
     ((192, 24, 24), (2, 2, 2)),
     ((128, 32, 32), (4, 4, 2)),
+    # d = 8 at rates other than 2 x 2 x 2 (the general 8-member instance)
+    ((32, 16, 16), (1, 2, 4)),
+    ((16, 16, 32), (4, 2, 1)),
     # s = 96 at every compile-time group size (d = 8, 16, 32)
     ((96, 24, 24), (2, 2, 2)),
     ((96, 16, 16), (2, 2, 4)),
