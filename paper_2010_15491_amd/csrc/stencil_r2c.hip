@@ -101,7 +101,8 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     else
       return roff[k];
   };
-  // Own points: row `row` of the tile, m = lane + 64 c.
+  // Own points: row `row` of the tile, m = CH lane + c (CH consecutive points
+  // per lane, so their loads, stores and LDS accesses are adjacent).
   const int gn = (n0 + row) % N;
   const bool rval = n0 + row < N;
   // Row n0-1 points: m = tid + kThreads j (< M).
@@ -125,7 +126,7 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     const uint32_t sb = (uint32_t)(((sp % S) + S) % S) * plane;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const uint32_t v = sb + (uint32_t)(gn * M + lane + 64 * c);
+      const uint32_t v = sb + (uint32_t)(gn * M + CH * lane + c);
       o[c][0] = ld_off(nui0, v);
       o[c][1] = ld_off(nui1, v);
       o[c][2] = ld_off(nui2, v);
@@ -161,7 +162,7 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = lane + 64 * c;
+      const int m = CH * lane + c;
       PointQ q;
       point_update_at<ANISO>(xs[0], xs[1], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
                              nup[c][0], nup[c][1], nup[c][2], a.thr, q);
@@ -182,18 +183,22 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     }
     __syncthreads();
     const uint32_t sb = (uint32_t)sp * plane;
-    float mw[CH], md[CH], mu[CH];  // m-components at the own points
-    float tw[CH], td[CH], tu[CH];  // s-term minus the point's own sum
+    float mw[CH], md[CH], mu[CH];     // m-components at the own points
+    float tw[CH], td[CH], tu[CH];     // s-term minus the point's own sum
+    float fnw[CH], fnd[CH], fnu[CH];  // n-components
+    float nn0[CH], nn1[CH], nn2[CH];  // nu_new
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = lane + 64 * c;
+      const int m = CH * lane + c;
       PointQ q;
       point_update_at<ANISO>(xs[bc], xs[bn], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
                              nuc[c][0], nuc[c][1], nuc[c][2], a.thr, q);
-      const int fi = (row + 1) * M + m;
-      fw[fi] = q.w[1];
-      fd[fi] = q.d[1];
-      fu[fi] = q.du[1];
+      fnw[c] = q.w[1];
+      fnd[c] = q.d[1];
+      fnu[c] = q.du[1];
+      nn0[c] = q.nn[0];
+      nn1[c] = q.nn[1];
+      nn2[c] = q.nn[2];
       mw[c] = q.w[0];
       md[c] = q.d[0];
       mu[c] = q.du[0];
@@ -203,13 +208,26 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
       pw[c] = q.w[2];
       pd[c] = q.d[2];
       pu[c] = q.du[2];
-      if (rval) {
-        const uint32_t v = sb + (uint32_t)(gn * M + m);
-        st_off(nuo0, v, q.nn[0]);
-        st_off(nuo1, v, q.nn[1]);
-        st_off(nuo2, v, q.nn[2]);
-        point_stats<ANISO>(q, acc);
-      }
+      if (rval) point_stats<ANISO>(q, acc);
+    }
+    // The lane's CH points are adjacent: each array is written as one run.
+    {
+      const int f0 = (row + 1) * M + CH * lane;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) fw[f0 + c] = fnw[c];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) fd[f0 + c] = fnd[c];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) fu[f0 + c] = fnu[c];
+    }
+    if (rval) {
+      const uint32_t v = sb + (uint32_t)(gn * M + CH * lane);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) st_off(nuo0, v + c, nn0[c]);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) st_off(nuo1, v + c, nn1[c]);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) st_off(nuo2, v + c, nn2[c]);
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
@@ -223,31 +241,24 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
         fu[m] = q.du[1];
       }
     }
-    // The m-neighbour (m - 1, wrapping) of lane l in chunk c is lane l - 1 of
-    // chunk c, or lane 63 of chunk c - 1 for lane 0: a rotation of the
-    // wavefront by one lane (lane l receives lane l - 1, lane 0 lane 63).
+    // The m-neighbour (m - 1, wrapping) of point c > 0 of a lane is its point
+    // c - 1; that of point 0 is the last point of lane l - 1, and for lane 0
+    // that of lane 63 (m = M - 1): a rotation of the wavefront by one lane.
     float lw[CH], ld[CH], lu[CH];
-    {
-      float rw[CH], rd[CH], ru[CH];
+    lw[0] = lane_prev(mw[CH - 1]);
+    ld[0] = lane_prev(md[CH - 1]);
+    lu[0] = lane_prev(mu[CH - 1]);
 #pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        rw[c] = lane_prev(mw[c]);
-        rd[c] = lane_prev(md[c]);
-        ru[c] = lane_prev(mu[c]);
-      }
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int cp = (c + CH - 1) % CH;
-        lw[c] = lane ? rw[c] : rw[cp];
-        ld[c] = lane ? rd[c] : rd[cp];
-        lu[c] = lane ? ru[c] : ru[cp];
-      }
+    for (int c = 1; c < CH; ++c) {
+      lw[c] = mw[c - 1];
+      ld[c] = md[c - 1];
+      lu[c] = mu[c - 1];
     }
     __syncthreads();
     float *z = xs[bz];  // FFT buffer: z[2 (i TP + t) + e] = Theta[t][2 i + e]
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = lane + 64 * c;
+      const int m = CH * lane + c;
       const int fi = row * M + m;  // the point's n-neighbour (row above)
       // (L^T z)[i] = (z_m[i - e_m] + z_n[i - e_n]) + (z_s[i - e_s] - sum_a z_a[i])
       const float ltw = (lw[c] + fw[fi]) + tw[c];
