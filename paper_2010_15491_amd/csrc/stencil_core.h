@@ -52,6 +52,13 @@ __device__ __forceinline__ float lane_prev(float v) {
                                                     0xF, 0xF, false));
 }
 
+// The value of lane (l + 1) mod 64: a DPP rotation of the wavefront left by
+// one lane.
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134 /* wave_rol:1 */,
+                                                    0xF, 0xF, false));
+}
+
 // Workgroup b of nb is dispatched to XCD b % 8; give every XCD a contiguous
 // range of tiles so neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -98,16 +105,14 @@ struct PointQ {
   float nn[3];        // nu_new
 };
 
-// One point of the update from x at the point (xc[ri]), at its m and n
-// successors (xc[rm], xc[rn]) and at its s successor (xn[ri]), and nu_old.
+// One point of the update from x at the point (xi), at its m, n and s
+// successors (xm, xn, xs), and nu_old.
 template <bool ANISO>
-__device__ __forceinline__ void point_update_at(const float *xc, const float *xn, int ri, int rm,
-                                                int rn, float o0, float o1, float o2, float thr,
-                                                PointQ &q) {
-  const float xi = xc[ri];
-  q.l[0] = xc[rm] - xi;
-  q.l[1] = xc[rn] - xi;
-  q.l[2] = xn[ri] - xi;
+__device__ __forceinline__ void point_update_x(float xi, float xm, float xn, float xs, float o0,
+                                               float o1, float o2, float thr, PointQ &q) {
+  q.l[0] = xm - xi;
+  q.l[1] = xn - xi;
+  q.l[2] = xs - xi;
   float uo0, uo1, uo2;
   shrink_tv<ANISO>(o0, o1, o2, thr, uo0, uo1, uo2);
   q.nn[0] = q.l[0] + (o0 - uo0);
@@ -121,6 +126,15 @@ __device__ __forceinline__ void point_update_at(const float *xc, const float *xn
     q.w[c] = q.u[c] - q.d[c];
     q.du[c] = q.u[c] - uo[c];
   }
+}
+
+// The same with x read from plane buffers: the point at xc[ri], its m and n
+// successors at xc[rm], xc[rn], its s successor at xn[ri].
+template <bool ANISO>
+__device__ __forceinline__ void point_update_at(const float *xc, const float *xn, int ri, int rm,
+                                                int rn, float o0, float o1, float o2, float thr,
+                                                PointQ &q) {
+  point_update_x<ANISO>(xc[ri], xc[rm], xc[rn], xn[ri], o0, o1, o2, thr, q);
 }
 
 // The point's terms of the residual sums: |Lx - u'|^2, |Lx|^2, |u'|^2 and

@@ -42,6 +42,24 @@ struct SRGeom {
   static_assert(H * TP * 2 <= XPLANE, "the FFT buffer fits one x plane buffer");
 };
 
+// The n consecutive floats at p (16-byte aligned for n = 4, 8-byte for n = 2)
+// as one LDS access.
+template <int n>
+__device__ __forceinline__ void lds_run(const float *p, float (&v)[n]) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  if constexpr (n == 4) {
+    const f32x4 r = *reinterpret_cast<const f32x4 *>(p);
+    v[0] = r.x; v[1] = r.y; v[2] = r.z; v[3] = r.w;
+  } else if constexpr (n == 2) {
+    const f32x2 r = *reinterpret_cast<const f32x2 *>(p);
+    v[0] = r.x; v[1] = r.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] = p[i];
+  }
+}
+
 // Tile b of the plan; the residual sums go to partial slot `slot`.
 template <int M, typename Acc, bool ANISO>
 __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const StencilPlan &pl,
@@ -53,7 +71,7 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
   using G = SRGeom<M>;
   constexpr int CH = G::CH, H = G::H, MH = G::MH, XPLANE = G::XPLANE, XPT = G::XPT;
   constexpr int FPT = G::FPT, TP = G::TP;
-  __shared__ float xs[3][XPLANE];
+  __shared__ __align__(16) float xs[3][XPLANE];
   __shared__ float fw[G::FPLANE], fd[G::FPLANE], fu[G::FPLANE];  // n-components
   __shared__ float2 stw[H], stwm[MH];
   __shared__ int sperm[MH];
@@ -144,6 +162,17 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
   auto idx = [](int rr, int m) { return rr * M + m; };
   auto idx_m1 = [](int rr, int m) { return rr * M + (m + 1 == M ? 0 : m + 1); };
 
+  // x at the lane's own points of a plane (xa), at their n successors (xb)
+  // and s successors (xz), from the plane buffers xc (this plane) and xn (the
+  // next); the m successor of the last point is the next lane's first point.
+  auto own_x = [&](const float *xc, const float *xn, float (&xa)[CH], float (&xb)[CH],
+                   float (&xz)[CH], float &xl) {
+    lds_run<CH>(xc + (row + 1) * M + CH * lane, xa);
+    lds_run<CH>(xc + (row + 2) * M + CH * lane, xb);
+    lds_run<CH>(xn + (row + 1) * M + CH * lane, xz);
+    xl = lane_next(xa[0]);
+  };
+
   float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float pw[CH], pd[CH], pu[CH];  // s-components at the previous plane
   float xr[XPT];
@@ -151,21 +180,22 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
 
   // Prologue: plane s0 - 1 (its s-components feed L^T at plane s0).
   {
-    float xa[XPT], nup[CH + FPT][3];
-    ring_fetch(s0 - 1, xa);
+    float xp[XPT], nup[CH + FPT][3];
+    ring_fetch(s0 - 1, xp);
     ring_fetch(s0, xr);
     nu_fetch(s0 - 1, nup);
-    ring_store(0, xa);
+    ring_store(0, xp);
     ring_store(1, xr);
     ring_fetch(s0 + 1, xr);
     nu_fetch(s0, nuc);
     __syncthreads();
+    float xa[CH], xb[CH], xz[CH], xl;
+    own_x(xs[0], xs[1], xa, xb, xz, xl);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = CH * lane + c;
       PointQ q;
-      point_update_at<ANISO>(xs[0], xs[1], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
-                             nup[c][0], nup[c][1], nup[c][2], a.thr, q);
+      point_update_x<ANISO>(xa[c], c + 1 < CH ? xa[c + 1] : xl, xb[c], xz[c], nup[c][0], nup[c][1],
+                            nup[c][2], a.thr, q);
       pw[c] = q.w[2];
       pd[c] = q.d[2];
       pu[c] = q.du[2];
@@ -187,12 +217,13 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     float tw[CH], td[CH], tu[CH];     // s-term minus the point's own sum
     float fnw[CH], fnd[CH], fnu[CH];  // n-components
     float nn0[CH], nn1[CH], nn2[CH];  // nu_new
+    float xa[CH], xb[CH], xz[CH], xl;
+    own_x(xs[bc], xs[bn], xa, xb, xz, xl);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = CH * lane + c;
       PointQ q;
-      point_update_at<ANISO>(xs[bc], xs[bn], idx(row + 1, m), idx_m1(row + 1, m), idx(row + 2, m),
-                             nuc[c][0], nuc[c][1], nuc[c][2], a.thr, q);
+      point_update_x<ANISO>(xa[c], c + 1 < CH ? xa[c + 1] : xl, xb[c], xz[c], nuc[c][0], nuc[c][1],
+                            nuc[c][2], a.thr, q);
       fnw[c] = q.w[1];
       fnd[c] = q.d[1];
       fnu[c] = q.du[1];
