@@ -139,8 +139,13 @@ struct Geometry {
   SolveSPlan sp;  // fused x-update plan (TV)
 };
 
-// Rates 2 x 2 x 2: the fused x-update has an instance specialised for them.
-static bool rates_222(const Geometry &g) { return g.dr == 2 && g.dc == 2 && g.ds == 2; }
+// The m and n rate of a volume whose group size is its plan's member bound and
+// whose rates are those an instance of the fused x-update is specialised for
+// (2 x 2 x 2, 2 x 2 x 4, 4 x 4 x 2), else 0.
+static int fixed_rate(const Geometry &g) {
+  const int r = g.sp.dm == 32 ? 4 : 2;
+  return (g.D == g.sp.dm && g.dr == r && g.dc == r) ? r : 0;
+}
 
 int check_geometry(sr3d_dims hr, sr3d_rate rate, const sr3d_dims *psf, Geometry *g) {
   if (hr.m < 1 || hr.n < 1 || hr.s < 1) return fail(SR3D_ERR_INVALID_ARG, "HR dimensions must be >= 1");
@@ -566,7 +571,7 @@ hipError_t wavelet_iteration(const Geometry &g, const TvWs &L, const sr3d_proble
                               carry && merged ? &red : nullptr)))
       return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, fixed_rate(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -642,7 +647,7 @@ hipError_t l1_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
       e = fft2d_mn_forward(L.theta, L.w, g.S, g.N, g.M, kofp, posk, g.sp.pitch, done, st, nullptr);
     if (e) return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, fixed_rate(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -713,7 +718,7 @@ hipError_t tv_iteration(const Geometry &g, const TvWs &L, const sr3d_problem *p,
                            carry && merged ? &red : nullptr);
     if (e) return e;
     prof_begin(kStSolveS, st);
-    e = solve_s(g.S, g.sp.dm, g.D, rates_222(g), L.sdesc, nullptr, g.sp.units, fp64, st);
+    e = solve_s(g.S, g.sp.dm, g.D, fixed_rate(g), L.sdesc, nullptr, g.sp.units, fp64, st);
     prof_end(st);
     if (e) return e;
     if ((e = fft2d_mn_inverse(L.w, p->x, g.S, g.N, g.M, 1.0f, kofp, posk, g.sp.pitch, done, st)))
@@ -952,9 +957,9 @@ size_t batch_items(const std::vector<Geometry> &g, const std::vector<char> &fuse
   for (int v = 0; v < n; ++v) {
     if (fused[v]) {
       // variant: 4 x member bound, +1 for the instance with the group size
-      // fixed, +2 for rates 2 x 2 x 2
+      // fixed, +2 for the instance with the m and n rates fixed as well
       auto &gr = group(8, g[v].S,
-                       4 * g[v].sp.dm + (g[v].D == g[v].sp.dm ? 1 : 0) + (rates_222(g[v]) ? 2 : 0));
+                       4 * g[v].sp.dm + (g[v].D == g[v].sp.dm ? 1 : 0) + (fixed_rate(g[v]) ? 2 : 0));
       for (int t = 0; t < g[v].sp.units; ++t) gr.items.push_back(make_int2(v, t));
       continue;
     }
@@ -1062,8 +1067,8 @@ hipError_t batch_iteration(const BatchPlan &plan, const BatchHeader &H,
     if (gr.kind != 8) continue;
     prof_begin(kStSolveS, st);
     const int dm = gr.variant / 4;
-    e = solve_s(gr.key, dm, (gr.variant & 1) ? dm : -1, (gr.variant & 2) != 0, H.solve,
-                items_of(gr), (int)gr.items.size(), fp64, st);
+    e = solve_s(gr.key, dm, (gr.variant & 1) ? dm : -1, (gr.variant & 2) ? (dm == 32 ? 4 : 2) : 0,
+                H.solve, items_of(gr), (int)gr.items.size(), fp64, st);
     prof_end(st);
     if (e) return e;
   }

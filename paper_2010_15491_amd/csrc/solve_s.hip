@@ -167,14 +167,14 @@ __global__ __launch_bounds__(kThreads) void k_solve_s_gather(SolveSArgs a,
   }
 }
 
-hipError_t solve_s(int S, int dm, int d, bool g2, const SolveSArgs *descs, const int2 *items,
+hipError_t solve_s(int S, int dm, int d, int gr, const SolveSArgs *descs, const int2 *items,
                    int nwg, bool fp64, hipStream_t st) {
   if (nwg == 0) return hipSuccess;
   if (!twiddles(S)) return hipErrorInvalidValue;
   switch (S) {
 #define SR3D_CASE(L)                                        \
   case L:                                                   \
-    solve_s_launch_##L(dm, d, g2, descs, items, nwg, fp64, st); \
+    solve_s_launch_##L(dm, d, gr, descs, items, nwg, fp64, st); \
     break;
     SR3D_SOLVE_S_LENGTHS(SR3D_CASE)
 #undef SR3D_CASE

@@ -123,7 +123,7 @@ struct UnitTabs {
   float gnv[64];    // (ji, b): |sigma_n(k_n)|^2
 };
 
-template <int S, int DM, bool EXACT, bool G2, typename Acc>
+template <int S, int DM, bool EXACT, int GR, typename Acc>
 __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
                                              const float2 *__restrict__ tw, float2 *lds,
                                              float2 *stw, float *sgs, UnitTabs &ut, Acc *red) {
@@ -244,9 +244,10 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
   const int gbase = ((int)threadIdx.x & 63) - sub;  // lane of member 0's owner
   constexpr int GT = kThreads / LANES;              // groups in flight per workgroup
   // member 8 sub -> (a, b, c) counters along m, n, s
-  // Rates along m and n: compile-time constants in the instance for
-  // d = 2 x 2 x 2, where every member's table indices then fold away.
-  const int GDR = G2 ? 2 : a.dr, GDC = G2 ? 2 : a.dc;
+  // Rates along m and n: compile-time constants (both GR) in the instances
+  // specialised for the common rates, where every member's table indices
+  // then fold away.
+  const int GDR = GR ? GR : a.dr, GDC = GR ? GR : a.dc;
   const int m0 = sub * DL, ia0 = m0 % GDR, ib0 = (m0 / GDR) % GDC, ic0 = m0 / (GDR * GDC);
   Acc resid = 0;
   // Lambda of member q of slot i at Lu + (q gmax + i) 8 bytes, Y of slot i at
@@ -521,8 +522,8 @@ __device__ __forceinline__ void solve_s_body(const SolveSArgs &a, int u,
 }
 
 // Two workgroups per CU (the LDS tile allows two); every instance holds 8
-// members per lane. G2: every volume of the launch has rates 2 x 2 x 2.
-template <int S, int DM, bool EXACT, bool G2, typename Acc>
+// members per lane. GR > 0: every volume of the launch has m and n rates GR.
+template <int S, int DM, bool EXACT, int GR, typename Acc>
 __global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__restrict__ descs,
                                                       const int2 *__restrict__ items,
                                                       const float2 *__restrict__ tw) {
@@ -542,47 +543,48 @@ __global__ __launch_bounds__(kThreads, 2) void k_solve_s(const SolveSArgs *__res
   __shared__ float sgs[S];
   __shared__ UnitTabs ut;
   __shared__ Acc red[kThreads / 64];
-  solve_s_body<S, DM, EXACT, G2, Acc>(a, u, tw, lds, stw, sgs, ut, red);
+  solve_s_body<S, DM, EXACT, GR, Acc>(a, u, tw, lds, stw, sgs, ut, red);
 }
 
+// The rate the exact instance of member bound DM is specialised for
+// (2 x 2 x 2, 2 x 2 x 4 and 4 x 4 x 2).
+constexpr int solve_s_fixed_rate(int dm) { return dm == 32 ? 4 : 2; }
+
 template <int S, int DM, typename Acc>
-static void launch_solve_s_dm(bool exact, bool g2, const SolveSArgs *descs, const int2 *items,
+static void launch_solve_s_dm(bool exact, int gr, const SolveSArgs *descs, const int2 *items,
                               int nwg, hipStream_t st) {
   const float2 *tw = twiddles(S);
-  if constexpr (DM == 8) {
-    if (exact && g2) {
-      hipLaunchKernelGGL((k_solve_s<S, DM, true, true, Acc>), dim3(nwg), dim3(kThreads), 0, st,
-                         descs, items, tw);
-      return;
-    }
-  }
-  if (exact)
-    hipLaunchKernelGGL((k_solve_s<S, DM, true, false, Acc>), dim3(nwg), dim3(kThreads), 0, st,
+  constexpr int GRF = solve_s_fixed_rate(DM);
+  if (exact && gr == GRF)
+    hipLaunchKernelGGL((k_solve_s<S, DM, true, GRF, Acc>), dim3(nwg), dim3(kThreads), 0, st,
                        descs, items, tw);
+  else if (exact)
+    hipLaunchKernelGGL((k_solve_s<S, DM, true, 0, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs,
+                       items, tw);
   else
-    hipLaunchKernelGGL((k_solve_s<S, DM, false, false, Acc>), dim3(nwg), dim3(kThreads), 0, st,
-                       descs, items, tw);
+    hipLaunchKernelGGL((k_solve_s<S, DM, false, 0, Acc>), dim3(nwg), dim3(kThreads), 0, st, descs,
+                       items, tw);
 }
 
 // dm: member bound of the plan; d: the group size (the instance with
-// D = dm fixed at compile time runs when d == dm); g2: every volume has
-// rates 2 x 2 x 2.
+// D = dm fixed at compile time runs when d == dm); gr: the m and n rate
+// shared by every volume of the launch, or 0.
 template <int S, typename Acc>
-static void launch_solve_s_t(int dm, int d, bool g2, const SolveSArgs *descs, const int2 *items,
+static void launch_solve_s_t(int dm, int d, int gr, const SolveSArgs *descs, const int2 *items,
                              int nwg, hipStream_t st) {
-  if (dm <= 8) launch_solve_s_dm<S, 8, Acc>(d == 8, g2, descs, items, nwg, st);
-  else if (dm <= 16) launch_solve_s_dm<S, 16, Acc>(d == 16, false, descs, items, nwg, st);
-  else launch_solve_s_dm<S, 32, Acc>(d == 32, false, descs, items, nwg, st);
+  if (dm <= 8) launch_solve_s_dm<S, 8, Acc>(d == 8, gr, descs, items, nwg, st);
+  else if (dm <= 16) launch_solve_s_dm<S, 16, Acc>(d == 16, gr, descs, items, nwg, st);
+  else launch_solve_s_dm<S, 32, Acc>(d == 32, gr, descs, items, nwg, st);
 }
 
 // One launcher per s-length, defined in the instantiating translation units.
 #define SR3D_SOLVE_S_LAUNCHER(L)                                                     \
-  void solve_s_launch_##L(int dm, int d, bool g2, const SolveSArgs *descs,             \
+  void solve_s_launch_##L(int dm, int d, int gr, const SolveSArgs *descs,              \
                           const int2 *items, int nwg, bool fp64, hipStream_t st)
 #define SR3D_SOLVE_S_DEFINE(L)                                                    \
   SR3D_SOLVE_S_LAUNCHER(L) {                                                      \
-    if (fp64) launch_solve_s_t<L, double>(dm, d, g2, descs, items, nwg, st);      \
-    else launch_solve_s_t<L, float>(dm, d, g2, descs, items, nwg, st);            \
+    if (fp64) launch_solve_s_t<L, double>(dm, d, gr, descs, items, nwg, st);      \
+    else launch_solve_s_t<L, float>(dm, d, gr, descs, items, nwg, st);            \
   }
 #define SR3D_SOLVE_S_LENGTHS(X) \
   X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)

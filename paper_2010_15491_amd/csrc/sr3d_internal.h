@@ -271,8 +271,9 @@ hipError_t solve_s_gather(const SolveSArgs &a, const float2 *lam, const float2 *
                           hipStream_t st);
 // descs: device array of per-volume arguments; items: (volume, unit) per
 // workgroup, or null for one volume (descs[0]) with `units` workgroups.
-// g2: every volume of the launch has rates 2 x 2 x 2 (a specialised instance).
-hipError_t solve_s(int S, int dm, int d, bool g2, const SolveSArgs *descs, const int2 *items,
+// gr: the m and n rate every volume of the launch shares, where an instance is
+// specialised for it (2 at member bounds 8 and 16, 4 at 32), else 0.
+hipError_t solve_s(int S, int dm, int d, int gr, const SolveSArgs *descs, const int2 *items,
                    int nwg, bool fp64, hipStream_t st);
 
 // Fused difference / shrink / dual / Theta pass (Algorithm 1 steps 5b, 5c and
