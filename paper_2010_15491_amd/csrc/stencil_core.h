@@ -39,6 +39,18 @@ __device__ __forceinline__ void st_off(float *base, uint32_t i, float v) {
   *(__attribute__((address_space(1))) float *)((__attribute__((address_space(1))) char *)base +
                                                (i << 2)) = v;
 }
+// The same as non-temporal accesses, for streams that are not read again
+// before much more data has passed through the caches (the ADMM state, read
+// and written once per iteration): they leave the last-level cache to the
+// spectrum and the Lambda table, which the next kernels read.
+__device__ __forceinline__ float ld_off_nt(const float *base, uint32_t i) {
+  return __builtin_nontemporal_load((__attribute__((address_space(1))) const float *)(
+      (__attribute__((address_space(1))) const char *)base + (i << 2)));
+}
+__device__ __forceinline__ void st_off_nt(float *base, uint32_t i, float v) {
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) float *)(
+                                     (__attribute__((address_space(1))) char *)base + (i << 2)));
+}
 __device__ __forceinline__ void st_off2(float2 *base, uint32_t i, float2 v) {
   const uint64_t bits = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
   *(__attribute__((address_space(1))) uint64_t *)((__attribute__((address_space(1))) char *)base +

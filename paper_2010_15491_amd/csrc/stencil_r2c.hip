@@ -139,15 +139,17 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     for (int k = 0; k < XPT; ++k)
       if (XPLANE % kThreads == 0 || tid + k * kThreads < XPLANE) xs[buf][tid + k * kThreads] = xr[k];
   };
-  // nu_old at the own points (CH) and the row n0-1 points (FPT) of plane sp
+  // nu_old at the own points (CH) and the row n0-1 points (FPT) of plane sp;
+  // the own points' state is streamed (non-temporal loads, and stores of
+  // nu_new), the row n0-1 points, which the tile above reads too, are not
   auto nu_fetch = [&](int sp, float (*o)[3]) {
     const uint32_t sb = (uint32_t)(((sp % S) + S) % S) * plane;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const uint32_t v = sb + (uint32_t)(gn * M + CH * lane + c);
-      o[c][0] = ld_off(nui0, v);
-      o[c][1] = ld_off(nui1, v);
-      o[c][2] = ld_off(nui2, v);
+      o[c][0] = ld_off_nt(nui0, v);
+      o[c][1] = ld_off_nt(nui1, v);
+      o[c][2] = ld_off_nt(nui2, v);
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
@@ -254,11 +256,11 @@ __device__ __forceinline__ void stencil_r2c_body(const AdmmStencilArgs &a, const
     if (rval) {
       const uint32_t v = sb + (uint32_t)(gn * M + CH * lane);
 #pragma unroll
-      for (int c = 0; c < CH; ++c) st_off(nuo0, v + c, nn0[c]);
+      for (int c = 0; c < CH; ++c) st_off_nt(nuo0, v + c, nn0[c]);
 #pragma unroll
-      for (int c = 0; c < CH; ++c) st_off(nuo1, v + c, nn1[c]);
+      for (int c = 0; c < CH; ++c) st_off_nt(nuo1, v + c, nn1[c]);
 #pragma unroll
-      for (int c = 0; c < CH; ++c) st_off(nuo2, v + c, nn2[c]);
+      for (int c = 0; c < CH; ++c) st_off_nt(nuo2, v + c, nn2[c]);
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
