@@ -217,8 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_wavelet_fused(const float *__restr
       const bool detail = row != 0 || (m % T) != 0;
       const float th = detail ? thr : 0.f;
       const long gi = gidx(e);
+      // The state nu is streamed (non-temporal): read and written once per
+      // iteration, it would only displace x, xbar and the spectrum from the
+      // last-level cache.
       if (MODE == 2) {
-        const float nu = nu_in[gi];
+        const float nu = __builtin_nontemporal_load(nu_in + gi);
         const float u = soft(nu, th);
         t[e] = u - (nu - u);
         continue;
@@ -226,14 +229,14 @@ __global__ __launch_bounds__(kThreads) void k_wavelet_fused(const float *__restr
       const float c = t[e];
       float dprev = 0.f, uold = 0.f;
       if (MODE == 0) {
-        const float nuo = nu_in[gi];
+        const float nuo = __builtin_nontemporal_load(nu_in + gi);
         uold = soft(nuo, th);
         dprev = nuo - uold;
       }
       const float nu = c + dprev;
       const float u = soft(nu, th);
       const float d = nu - u;
-      nu_out[gi] = nu;
+      __builtin_nontemporal_store(nu, nu_out + gi);
       t[e] = u - d;
       if (MODE == 0) {
         const float rp = c - u, du = u - uold;
