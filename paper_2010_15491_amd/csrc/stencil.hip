@@ -112,13 +112,21 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
     for (int k = 0; k < XR_PT; ++k)
       if (ridx[k] < XR) xs[buf][ridx[k]] = xr[k];
   };
-  // nu_old at the 2 tile points and the face point of plane sp
+  // nu_old at the 2 tile points and the face point of plane sp. The tile
+  // points' state is streamed (non-temporal, as are the stores of nu_new):
+  // read and written once per iteration, it would only displace the spectrum
+  // and x from the last-level cache. The face points, which a neighbouring
+  // tile reads too, are not.
   auto nu_fetch = [&](int sp, float (*o)[3]) {
     const long sb = (long)(((sp % S) + S) % S) * plane;
     const long offs[3] = {sb + poff[0], sb + poff[1], sb + foff};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (a.nu_in && (k < 2 || has_face)) {
+      if (a.nu_in && k < 2) {
+        o[k][0] = __builtin_nontemporal_load(a.nu_in + offs[k]);
+        o[k][1] = __builtin_nontemporal_load(a.nu_in + offs[k] + NT);
+        o[k][2] = __builtin_nontemporal_load(a.nu_in + offs[k] + 2 * NT);
+      } else if (a.nu_in && has_face) {
         o[k][0] = a.nu_in[offs[k]];
         o[k][1] = a.nu_in[offs[k] + NT];
         o[k][2] = a.nu_in[offs[k] + 2 * NT];
@@ -187,9 +195,9 @@ __device__ __forceinline__ void stencil_body(const AdmmStencilArgs &a, const Ste
       pu[k] = q.du[2];
       if (pval[k]) {
         const long v = sb + poff[k];
-        a.nu_out[v] = q.nn[0];
-        a.nu_out[v + NT] = q.nn[1];
-        a.nu_out[v + 2 * NT] = q.nn[2];
+        __builtin_nontemporal_store(q.nn[0], a.nu_out + v);
+        __builtin_nontemporal_store(q.nn[1], a.nu_out + v + NT);
+        __builtin_nontemporal_store(q.nn[2], a.nu_out + v + 2 * NT);
         if (STATS) {
           point_stats<ANISO>(q, acc);
         }
