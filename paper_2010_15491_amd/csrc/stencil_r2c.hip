@@ -9,8 +9,10 @@
 //   - x of the rows n0-1 .. n0+SR_ROWS is staged in LDS (three rotating plane
 //     buffers; m wraps inside the row, so no m ring is needed);
 //   - nu_new, u', d' are formed for the tile and for row n0-1, whose
-//     n-components feed L^T at row n0; the m-neighbour values L^T needs come
-//     from the lane to the left by a cross-lane shuffle;
+//     n-components feed L^T at row n0; a lane owns M/64 adjacent points of
+//     its row, so the m-neighbour values L^T needs are its own points but
+//     for the first, which comes from the lane to the left by a cross-lane
+//     shuffle;
 //   - Theta of the plane's rows goes into the plane buffer not in use, which
 //     is then transformed along m as a half-length complex FFT and written out.
 // The pointwise arithmetic is that of the tiled stencil (stencil_core.h) and
